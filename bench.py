@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Benchmark of the cone-beam TV reconstruction hot path on one MI355X.
+
+One step = one complete reconstruction (cbct_fbs_solve) of the head-sized
+workload: 512x512x70 volume (0.88 x 0.88 x 2.5 mm), 40 views over 360
+degrees on a 512x384 detector (0.776 mm), SAD 1000 / SDD 1500 mm, Poisson
+noise I0 = 5e4 on a seeded random-ellipsoid head, mu = 1e-3, two-level
+coarse-to-fine schedule 256x256x35 then 512x512x70 with 20 + 20 iterations,
+energies traced every iteration.  It runs every step of the path: forward
+projection with residual, gather-form transpose fused with Step 1, the
+projected TV sweeps, the energies, the multigrid transfers; beta comes from
+the power iteration (computed in the warm-up solve and cached by the plan).
+
+`value` is the whole-solve throughput in GRay-samples/s: ray samples of
+all projector and transpose applications in one solve divided by the wall
+time of the solve, inputs resident in HBM.  Printed as ONE JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+METRIC = ("GRay-samples/s for P and P^T (%HBM peak); recon s/volume; "
+          "served p50/p99 latency")
+PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+PEAK_ALU_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, non-packed
+# algorithmic floating-point operations per ray sample of the projector and
+# of the transpose's cell pass (coordinate FMAs, floors, fractions, the
+# trilinear weights and the accumulation; counted in the design doc)
+FLOPS_PER_SAMPLE = 34.0
+TV_BYTES_PER_VOXEL = 12.0   # read z and g, write z
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-views", type=int, default=4,
+                    help="views of the head scan the CPU oracle sample uses")
+    ap.add_argument("--ops-reps", type=int, default=10)
+    return ap.parse_args()
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def coarse_of(g):
+    import dataclasses
+    return dataclasses.replace(g, nx=g.nx // 2, ny=g.ny // 2, nz=g.nz // 2, hx=2 * g.hx,
+                               hy=2 * g.hy, hz=2 * g.hz, nu=g.nu // 2, nv=g.nv // 2,
+                               au=2 * g.au, av=2 * g.av,
+                               step=2 * (g.step if g.step > 0 else 0.5 * min(g.hx, g.hy, g.hz)))
+
+
+def time_op(torch, fn, reps):
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(case_geom, Y, views):
+    """The FP64 oracle (P then P^T) on the first `views` views of the scan."""
+    import dataclasses
+    import numpy as np
+    import oracle
+    g = dataclasses.replace(case_geom, n_views=views,
+                            angles=tuple(2 * math.pi * k / case_geom.n_views
+                                         for k in range(views)))
+    rng = np.random.default_rng(0)
+    f = rng.uniform(0.0, 0.02, g.vol_shape)
+    y = np.ascontiguousarray(Y[:views])
+    s = oracle.count_samples(g)
+    t0 = time.perf_counter()
+    oracle.project(g, f)
+    t1 = time.perf_counter()
+    oracle.backproject(g, y)
+    t2 = time.perf_counter()
+    return {"value": 2.0 * s / (t2 - t0) / 1e9, "unit": "GRay-samples/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": "FP64 oracle P and scatter P^T over views 0-%d of the 40-view "
+                      "head scan (%d ray samples each; P %.2f s, P^T %.2f s)"
+                      % (views - 1, s, t1 - t0, t2 - t1)}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the reconstruction path runs on a single "
+              "MI355X (multi-GPU sharding by views is described in DESIGN.md, not built); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_1002_3675_amd as cb
+    from workloads import head_case
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a HIP device")
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    t = time.perf_counter()
+    case = head_case(40, iters=(20, 20))
+    g = case.geom
+    log("synthetic head data in %.1f s" % (time.perf_counter() - t))
+    Y = torch.as_tensor(case.Y, dtype=torch.float32, device=dev).contiguous()
+    plan = cb.Plan(g)
+    plan_c = cb.Plan(coarse_of(g))
+    s_f, s_c = plan.samples, plan_c.samples
+    iters = case.iters
+    params = cb.FbsParams(mu=case.mu, iters=iters, eps=case.eps, trace_energy=True)
+    # ray samples per solve: per level, iters+1 projections (one per
+    # iteration plus the final energy) and iters transposes
+    samples_per_step = (2 * iters[0] + 1) * s_c + (2 * iters[1] + 1) * s_f
+
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    f, rep = cb.fbs_solve(plan, Y, params)   # includes beta (power iteration)
+    torch.cuda.synchronize()
+    first_s = time.perf_counter() - t
+    log("first solve (with beta setup) %.3f s, beta %s, inner %s"
+        % (first_s, rep.beta_used, rep.n_inner_used))
+    for _ in range(max(0, args.warmup - 1)):
+        cb.fbs_solve(plan, Y, params)
+    torch.cuda.synchronize()
+
+    cb.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        f, rep = cb.fbs_solve(plan, Y, params)
+        log("step %d done" % i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cb.kernel_timing(False)
+    ktimes = cb.kernel_times()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = samples_per_step / (ms_per_step * 1e-3) / 1e9
+
+    # per-kernel algorithmic work over the timed region
+    nvox_f, nvox_c = g.n_vox, plan_c.geom.nx * plan_c.geom.ny * plan_c.geom.nz
+    sweeps = rep.n_inner_used[0] * iters[0] * nvox_c + rep.n_inner_used[1] * iters[1] * nvox_f
+    work = {
+        "project": ("alu", FLOPS_PER_SAMPLE * ((iters[0] + 1) * s_c + (iters[1] + 1) * s_f)),
+        "cells": ("alu", FLOPS_PER_SAMPLE * (iters[0] * s_c + iters[1] * s_f)),
+        "tv_sweep": ("hbm", TV_BYTES_PER_VOXEL * sweeps),
+        "gather": ("hbm", 4.0 * (8 + 1 + 1) * (iters[0] * nvox_c + iters[1] * nvox_f)),
+    }
+    dom = max(ktimes, key=lambda k: ktimes[k][1])
+    per_kernel = {k: {"launches": n // args.steps, "ms_per_step": tot / args.steps}
+                  for k, (n, tot) in ktimes.items()}
+    roofline = None
+    if dom in work:
+        bound, per_step = work[dom]
+        n, tot_ms = ktimes[dom]
+        avg_ms = tot_ms / max(n, 1)
+        per_launch = per_step / max(n // args.steps, 1)
+        if bound == "alu":
+            achieved = per_launch / (avg_ms * 1e-3) / 1e12
+            roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
+                        "traffic": None, "kernel": dom, "avg_launch_ms": avg_ms}
+        else:
+            achieved = per_launch / (avg_ms * 1e-3) / 1e9
+            roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                        "traffic": None, "kernel": dom, "avg_launch_ms": avg_ms}
+
+    # stand-alone operator throughput at the fine level
+    fr = torch.rand(g.vol_shape, device=dev) * 0.02
+    yr = torch.rand(g.proj_shape, device=dev) * 4.0
+    yb = torch.empty_like(yr)
+    fb = torch.empty_like(fr)
+    ms_p = time_op(torch, lambda: plan.project(fr, out=yb), args.ops_reps)
+    ms_pt = time_op(torch, lambda: plan.backproject(yr, out=fb), args.ops_reps)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GRay-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "head 512x512x70 @0.88x0.88x2.5 mm, 40 views/360 deg, 512x384 "
+                        "detector @0.776 mm, SAD/SDD 1000/1500 mm, Poisson I0=5e4, "
+                        "mu=1e-3, 2-level FBS 20+20 iterations (256x256x35 -> 512x512x70)",
+            "samples_per_solve": samples_per_step,
+            "samples_fine": s_f,
+            "samples_coarse": s_c,
+        },
+        "recon_s_per_volume": ms_per_step / 1e3,
+        "first_solve_s_with_beta_setup": first_s,
+        "beta_used": list(rep.beta_used),
+        "n_inner_used": list(rep.n_inner_used),
+        "final_energy": rep.E,
+        "P_fine_ms": ms_p,
+        "P_fine_grays": s_f / (ms_p * 1e-3) / 1e9,
+        "PT_fine_ms": ms_pt,
+        "PT_fine_grays": s_f / (ms_pt * 1e-3) / 1e9,
+        "per_kernel": per_kernel,
+        "roofline": roofline,
+        "paper_context": "77-130 s per reconstruction on a Tesla C1060 (different "
+                         "hardware, phantom and iteration count; not a target)",
+    }
+    if not args.no_cpu_baseline:
+        t = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(g, case.Y, args.cpu_views)
+        log("cpu baseline %.1f s" % (time.perf_counter() - t))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -78,8 +78,15 @@ def _load():
                                          _I, _D, ctypes.c_double, _I, ctypes.c_double,
                                          ctypes.c_int, _D, _D, _D]
             lib.or_fbs_solve.restype = ctypes.c_int
+            lib.or_threads.argtypes = []
+            lib.or_threads.restype = ctypes.c_int
             _lib = lib
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(_load().or_threads())
 
 
 def _dp(a):

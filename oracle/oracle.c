@@ -617,3 +617,13 @@ int or_fbs_solve(const int *dims, const double *par, const double *angles,
     free(fcoarse);
     return 0;
 }
+
+/* Number of OpenMP threads the parallel loops above use. */
+int or_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,116 @@
+// Internal declarations of the MI355X cone-beam library: per-view constants,
+// the ray/sample arithmetic shared by the projector and its transpose, and
+// the host-side launchers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/cbct.h"
+
+namespace cbct {
+
+// Per-view constants, in voxel-index units where noted.  A sample n on the
+// ray through pixel (u, v) lies at voxel-index coordinate
+//     q_a(n) = Q_a + n * D_a,      D_a = (W_a + u U_a + v V_a) / |dir|,
+// with |dir| = sqrt(sdd^2 + u^2 + v^2): the source-to-pixel direction
+// sdd*e_w + u*e_u + v*e_v has orthonormal components.  Q is the source
+// position in index coordinates, (s_a - x_a(0)) / h_a, and W, U, V are
+// step/h_a times sdd*e_w, e_u and e_v.
+struct ViewConst {
+    float Q[3];
+    float W[2];    // W_z = 0 (e_w lies in the xy plane)
+    float U[2];    // U_z = 0
+    float Vz;      // V_x = V_y = 0
+    float src[2];  // source (mm), x and y; z = 0
+    float cs, sn;  // cos(theta), sin(theta)
+    double Qd[3];  // the same constants in double for the FP64 kernels
+    double Wd[2], Ud[2], Vzd;
+    double pad_;
+};
+
+struct DetConst {
+    float u0, au, v0, av;  // pixel centre u = u0 + i*au, v = v0 + j*av (mm)
+    float sdd2;            // sdd^2
+    float sdd;
+    double u0d, aud, v0d, avd, sdd2d;
+};
+
+struct GridConst {
+    int nx, ny, nz;
+    float hx, hy, hz;
+    float x0, y0, z0;      // centre of voxel 0 (mm)
+};
+
+}  // namespace cbct
+
+struct cbct_plan {
+    cbct_geom g;                      // resolved (step filled, angles -> copy)
+    std::vector<double> angles;
+    cbct::ViewConst *d_views = nullptr;   // device [n_views]
+    std::vector<cbct::ViewConst> h_views;
+    cbct::DetConst det;
+    cbct::GridConst grid;
+    int64_t samples = 0;
+    int device = 0;
+    mutable std::mutex lam_mu;
+    mutable std::vector<std::pair<int, double>> lam_cache;
+    // coarse level of the two-level schedule, created on first use
+    mutable std::mutex coarse_mu;
+    mutable cbct_plan *coarse = nullptr;
+};
+
+namespace cbct {
+
+// ----------------------------------------------------------- errors --------
+int set_error(int code, const std::string &msg);
+int check_hip(hipError_t e, const char *what);
+
+// ----------------------------------------------------------- memory --------
+// Stream-ordered scratch from a library-owned pool on the current device.
+hipError_t scratch_alloc(void **p, size_t bytes, hipStream_t s);
+hipError_t scratch_free(void *p, hipStream_t s);
+
+// ----------------------------------------------------------- launchers -----
+// All launchers enqueue on `s` and return the launch status.
+template <typename T>
+hipError_t launch_pad(const cbct_plan &p, const T *f, T *fpad, hipStream_t s);
+template <typename T>
+hipError_t launch_project(const cbct_plan &p, const T *fpad, const T *Y, T *out,
+                          double *partials, hipStream_t s);
+template <typename T>
+hipError_t launch_backproject_cells(const cbct_plan &p, const T *r, T *cells, hipStream_t s);
+template <typename T>
+hipError_t launch_gather_cells(const cbct_plan &p, const T *cells, const T *f, double tau,
+                               T *out, hipStream_t s);
+hipError_t launch_count_samples(const cbct_plan &p, unsigned long long *count, hipStream_t s);
+
+size_t project_partials_count(const cbct_plan &p);
+size_t cells_count(const cbct_plan &p);
+
+hipError_t launch_tv_sweep(const GridConst &gc, const float *z, const float *g, float *out,
+                           float beta, float eps, float step, int nonneg, hipStream_t s);
+hipError_t launch_tv_energy(const GridConst &gc, const float *z, double eps,
+                            double *partials, int *n_partials, hipStream_t s);
+hipError_t launch_reduce_sum(const double *partials, int n, double *out, int n_out_cols,
+                             hipStream_t s);
+size_t tv_energy_partials_count(const GridConst &gc);
+
+hipError_t launch_sumsq(const float *x, size_t n, double *partials, int *n_partials,
+                        hipStream_t s);
+hipError_t launch_fill(float *x, size_t n, float v, hipStream_t s);
+hipError_t launch_scale(const float *x, size_t n, const double *denom, float *out,
+                        hipStream_t s);
+hipError_t launch_bin_detector(const float *y, int nu, int nv, int nviews, float *out,
+                               hipStream_t s);
+hipError_t launch_restrict(const float *f, int nx, int ny, int nz, float *out, hipStream_t s);
+hipError_t launch_prolong(const float *fc, int cx, int cy, int cz, float *ff, int nx, int ny,
+                          int nz, hipStream_t s);
+
+GridConst grid_of(const cbct_geom &g);
+
+}  // namespace cbct

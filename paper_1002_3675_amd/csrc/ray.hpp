@@ -1,0 +1,120 @@
+// Ray and sample arithmetic shared by the projector and its transpose.
+//
+// Both kernels must agree on which interpolation cell every sample falls
+// in, so the sample coordinate is produced by one function, with floating
+// point contraction disabled and explicit fused multiply-adds, and the cell
+// is always floor() of that coordinate.  Then the gather-form transpose
+// enumerates exactly the (ray, sample) pairs the projector visits.
+//
+// Sample coordinates are computed in double precision whatever the data
+// type: a sample about 1000 mm from the source needs its direction to
+// ~1e-9 relative to land within 1e-5 voxel of its true position, beyond
+// float's 24-bit mantissa.  Double FMA, floor and convert run at the same
+// vector rate as non-packed float on gfx950.  The float variant of
+// ray_setup only feeds conservative range estimates.
+#pragma once
+
+#include "cbct_internal.hpp"
+
+namespace cbct {
+
+// Index-space origin Q and per-sample increment D of the ray through
+// pixel (i, j) of view vc (see ViewConst).
+__device__ __forceinline__ void ray_setup(const ViewConst &vc, const DetConst &dc, int i, int j,
+                                          float Q[3], float D[3]) {
+#pragma clang fp contract(off)
+    const float u = __builtin_fmaf((float)i, dc.au, dc.u0);
+    const float v = __builtin_fmaf((float)j, dc.av, dc.v0);
+    const float l2 = __builtin_fmaf(u, u, __builtin_fmaf(v, v, dc.sdd2));
+    const float inv = __builtin_amdgcn_rsqf(l2);
+    D[0] = __builtin_fmaf(u, vc.U[0], vc.W[0]) * inv;
+    D[1] = __builtin_fmaf(u, vc.U[1], vc.W[1]) * inv;
+    D[2] = (v * vc.Vz) * inv;
+    Q[0] = vc.Q[0];
+    Q[1] = vc.Q[1];
+    Q[2] = vc.Q[2];
+}
+
+__device__ __forceinline__ void ray_setup(const ViewConst &vc, const DetConst &dc, int i, int j,
+                                          double Q[3], double D[3]) {
+#pragma clang fp contract(off)
+    const double u = __builtin_fma((double)i, dc.aud, dc.u0d);
+    const double v = __builtin_fma((double)j, dc.avd, dc.v0d);
+    const double l2 = __builtin_fma(u, u, __builtin_fma(v, v, dc.sdd2d));
+    const double inv = 1.0 / __builtin_sqrt(l2);
+    D[0] = __builtin_fma(u, vc.Ud[0], vc.Wd[0]) * inv;
+    D[1] = __builtin_fma(u, vc.Ud[1], vc.Wd[1]) * inv;
+    D[2] = (v * vc.Vzd) * inv;
+    Q[0] = vc.Qd[0];
+    Q[1] = vc.Qd[1];
+    Q[2] = vc.Qd[2];
+}
+
+// Voxel-index coordinate of sample n along one axis.
+__device__ __forceinline__ float sample_coord(float n, float D, float Q) {
+    return __builtin_fmaf(n, D, Q);
+}
+__device__ __forceinline__ double sample_coord(double n, double D, double Q) {
+    return __builtin_fma(n, D, Q);
+}
+
+template <typename T>
+__device__ __forceinline__ T floor_t(T x);
+template <>
+__device__ __forceinline__ float floor_t<float>(float x) { return __builtin_floorf(x); }
+template <>
+__device__ __forceinline__ double floor_t<double>(double x) { return __builtin_floor(x); }
+
+// Interval [lo, hi] (real-valued, unrounded) of sample indices whose
+// coordinate along one axis lies in [a, b); returns false if none can.
+template <typename T>
+__device__ __forceinline__ bool axis_interval(T Q, T D, T a, T b, T &lo, T &hi) {
+    if (D > T(0)) {
+        T inv = T(1) / D;
+        lo = (a - Q) * inv;
+        hi = (b - Q) * inv;
+        return true;
+    }
+    if (D < T(0)) {
+        T inv = T(1) / D;
+        lo = (b - Q) * inv;
+        hi = (a - Q) * inv;
+        return true;
+    }
+    lo = T(-1e30);
+    hi = T(1e30);
+    return Q >= a && Q < b;
+}
+
+// Conservative float estimate of the sample indices whose coordinate along
+// one axis lies in [a, a + 1), for a ray given in float (Q, D).  The float
+// ray differs from the double one by at most ~1e-6 relative in Q and D, so
+// the true bounds (a - Q)/D move by at most 1e-6 (|Q| + |a| + 1) / |D|;
+// the interval is widened by four times that plus 1e-3.  Returns false
+// when no sample can have that coordinate.
+__device__ __forceinline__ bool axis_estimate(float Q, float D, float a, float &lo, float &hi) {
+    if (D == 0.0f) {
+        lo = -1e30f;
+        hi = 1e30f;
+        // q = Q exactly for every n in double too (D is exactly zero there
+        // only when the double D is zero as well: both come from u = 0 or
+        // v = 0 for the same pixel)
+        return Q >= a - 1e-3f && Q < a + 1.0f + 1e-3f;
+    }
+    const float inv = 1.0f / D;
+    const float m = 1e-3f + 4e-6f * (fabsf(Q) + fabsf(a) + 1.0f) * fabsf(inv);
+    const float t0 = (a - Q) * inv, t1 = (a + 1.0f - Q) * inv;
+    lo = fminf(t0, t1) - m;
+    hi = fmaxf(t0, t1) + m;
+    return true;
+}
+
+// Clamp a real sample index into a range safe for int conversion.
+template <typename T>
+__device__ __forceinline__ int clamp_to_int(T x) {
+    x = x < T(-4) ? T(-4) : x;
+    x = x > T(1 << 24) ? T(1 << 24) : x;
+    return (int)x;
+}
+
+}  // namespace cbct

@@ -1,0 +1,176 @@
+"""GPU parity of the projector P and its gather-form transpose P^T against
+the FP64 oracle (relative L2 <= 1e-5 in float32), dot tests, determinism,
+edge cases and the full head-size geometry on sampled views."""
+
+import dataclasses
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import Geometry, tiny_geometry, head_geometry, diff_geometry
+
+from gpu_util import require_gpu, rel_l2, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+RAGGED = Geometry(70, 45, 33, 2.1, 2.3, 2.7, 97, 61, 2.4, 2.2, 700.0, 1100.0, 7,
+                  angles=(0.05, 0.9, 1.7, 2.6, 3.3, 4.4, 5.9))
+
+
+def _plan(g):
+    import paper_1002_3675_amd as cb
+    return cb.Plan(g)
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("name,g", [("tiny", tiny_geometry()), ("ragged", RAGGED)])
+def test_project_matches_oracle(name, g):
+    require_gpu()
+    _log("project parity %s" % name)
+    rng = np.random.default_rng(10)
+    f = rng.uniform(0.0, 0.02, g.vol_shape)
+    plan = _plan(g)
+    y = to_np(plan.project(to_dev(f)))
+    want = oracle.project(g, f.astype(np.float32).astype(np.float64))
+    assert rel_l2(y, want) <= TOL, rel_l2(y, want)
+    assert plan.samples == oracle.count_samples(g) or \
+        abs(plan.samples - oracle.count_samples(g)) <= 1e-6 * plan.samples
+
+
+@pytest.mark.parametrize("name,g", [("tiny", tiny_geometry()), ("ragged", RAGGED)])
+def test_backproject_matches_oracle(name, g):
+    require_gpu()
+    _log("backproject parity %s" % name)
+    rng = np.random.default_rng(11)
+    y = rng.uniform(0.0, 4.0, g.proj_shape).astype(np.float32).astype(np.float64)
+    plan = _plan(g)
+    f = to_np(plan.backproject(to_dev(y)))
+    want = oracle.backproject(g, y)
+    assert rel_l2(f, want) <= TOL, rel_l2(f, want)
+
+
+def test_backproject_signed_residual():
+    """Mixed-sign input (a residual) still meets the tolerance."""
+    require_gpu()
+    g = tiny_geometry()
+    rng = np.random.default_rng(12)
+    y = rng.standard_normal(g.proj_shape).astype(np.float32).astype(np.float64)
+    f = to_np(_plan(g).backproject(to_dev(y)))
+    want = oracle.backproject(g, y)
+    assert rel_l2(f, want) <= TOL, rel_l2(f, want)
+
+
+def test_float32_dot_product():
+    require_gpu()
+    g = tiny_geometry()
+    plan = _plan(g)
+    rng = np.random.default_rng(13)
+    f = to_dev(rng.uniform(0, 0.02, g.vol_shape))
+    y = to_dev(rng.uniform(0, 4, g.proj_shape))
+    a = math.fsum((to_np(plan.project(f)) * to_np(y)).ravel())
+    b = math.fsum((to_np(f) * to_np(plan.backproject(y))).ravel())
+    assert abs(a - b) <= 2e-6 * abs(a), (a, b)
+
+
+def test_float64_kernels_match_oracle_tightly():
+    require_gpu()
+    import torch
+    g = RAGGED
+    plan = _plan(g)
+    rng = np.random.default_rng(14)
+    f = rng.uniform(0, 0.02, g.vol_shape)
+    y = rng.uniform(0, 4, g.proj_shape)
+    yp = to_np(plan.project(to_dev(f, torch.float64)))
+    assert rel_l2(yp, oracle.project(g, f)) <= 1e-12
+    fb = to_np(plan.backproject(to_dev(y, torch.float64)))
+    assert rel_l2(fb, oracle.backproject(g, y)) <= 1e-12
+
+
+def test_deterministic_bitwise():
+    require_gpu()
+    import torch
+    g = tiny_geometry()
+    plan = _plan(g)
+    rng = np.random.default_rng(15)
+    y = to_dev(rng.standard_normal(g.proj_shape))
+    f = to_dev(rng.uniform(0, 0.02, g.vol_shape))
+    a, b = plan.backproject(y), plan.backproject(y)
+    assert torch.equal(a, b)
+    assert torch.equal(plan.project(f), plan.project(f))
+
+
+def test_edge_cases():
+    require_gpu()
+    import torch
+    # zero volume -> zero projections; single view; 1-voxel-thick grid
+    g = Geometry(9, 7, 1, 3.0, 3.0, 3.0, 11, 3, 4.0, 4.0, 400.0, 700.0, 1, angles=(0.4,))
+    plan = _plan(g)
+    assert float(plan.project(torch.zeros(g.vol_shape, device="cuda")).abs().max()) == 0.0
+    rng = np.random.default_rng(16)
+    f = rng.uniform(0, 1, g.vol_shape)
+    assert rel_l2(to_np(plan.project(to_dev(f))), oracle.project(g, f)) <= TOL
+    y = rng.uniform(0, 1, g.proj_shape)
+    assert rel_l2(to_np(plan.backproject(to_dev(y))), oracle.backproject(g, y)) <= TOL
+    # detector that misses the grid entirely: all-zero output, no fault
+    g2 = Geometry(8, 8, 8, 1.0, 1.0, 1.0, 4, 4, 1.0, 1.0, 300.0, 500.0, 2, angles=(0.0, 1.0))
+    g2 = dataclasses.replace(g2, nv=2, av=400.0)  # both rows far above/below the grid
+    p2 = _plan(g2)
+    assert float(p2.project(torch.ones(g2.vol_shape, device="cuda")).abs().max()) == 0.0
+    assert float(p2.backproject(torch.ones(g2.proj_shape, device="cuda")).abs().max()) == 0.0
+    # shape and dtype errors are raised, not run
+    with pytest.raises(ValueError):
+        plan.project(torch.zeros((1, 2, 3), device="cuda"))
+    with pytest.raises(TypeError):
+        plan.project(torch.zeros(g.vol_shape, device="cuda", dtype=torch.float16))
+
+
+def test_head_size_projection_sampled_views():
+    """512x512x70 grid, 512x384 detector: views 0 and 13 of the 40-view scan
+    against the oracle run on those views only."""
+    require_gpu()
+    g = head_geometry(40)
+    plan = _plan(g)
+    rng = np.random.default_rng(17)
+    f = rng.uniform(0, 0.02, g.vol_shape).astype(np.float32)
+    y = to_np(plan.project(to_dev(f)))
+    f64 = f.astype(np.float64)
+    for k in (0, 13):
+        _log("head view %d" % k)
+        gk = dataclasses.replace(g, n_views=1, angles=(2 * math.pi * k / 40,))
+        want = oracle.project(gk, f64)[0]
+        assert rel_l2(y[k], want) <= TOL, (k, rel_l2(y[k], want))
+
+
+def test_head_size_backprojection_one_view():
+    """Full 512x512x70 transpose of data on one view (others zero)."""
+    require_gpu()
+    g = head_geometry(40)
+    plan = _plan(g)
+    rng = np.random.default_rng(18)
+    y = np.zeros(g.proj_shape, dtype=np.float32)
+    k = 7
+    y[k] = rng.uniform(0, 4, (g.nv, g.nu))
+    f = to_np(plan.backproject(to_dev(y)))
+    gk = dataclasses.replace(g, n_views=1, angles=(2 * math.pi * k / 40,))
+    want = oracle.backproject(gk, y[k:k + 1].astype(np.float64))
+    assert rel_l2(f, want) <= TOL, rel_l2(f, want)
+
+
+def test_diff_size_transpose_matches_oracle():
+    """128^3, 60 views, 256x192 (the differentiation workload)."""
+    require_gpu()
+    g = diff_geometry()
+    plan = _plan(g)
+    rng = np.random.default_rng(19)
+    y = rng.uniform(0, 4, g.proj_shape).astype(np.float32).astype(np.float64)
+    f = to_np(plan.backproject(to_dev(y)))
+    assert rel_l2(f, oracle.backproject(g, y)) <= TOL
