@@ -191,7 +191,8 @@ int validate_geom(const cbct_geom *g) {
     if (!(g->sad > sqrt(hx * hx + hy * hy)))
         return set_error(CBCT_EINVAL, "source orbit must lie outside the grid");
     const double padded = (double)(g->nx + 2) * (g->ny + 2) * (g->nz + 2);
-    if (padded > 2.0e9) return set_error(CBCT_EINVAL, "grid too large");
+    // float volumes are addressed with 32-bit byte offsets
+    if (padded * 4.0 > 2147483647.0) return set_error(CBCT_EINVAL, "grid too large");
     if ((double)g->nu * g->nv > 2.0e9) return set_error(CBCT_EINVAL, "detector too large");
     if (g->angles)
         for (int k = 0; k < g->n_views; ++k)
@@ -330,7 +331,7 @@ int project_impl(const cbct_plan *p, const T *f, const T *Y, T *out, double *sum
                  hipStream_t s) {
     if (!p || !f || !out) return set_error(CBCT_EINVAL, "NULL argument");
     Scratch pad(s), part(s);
-    int rc = check_hip(pad.alloc(sizeof(T) * padded_of(p->g)), "scratch (padded volume)");
+    int rc = check_hip(pad.alloc(sizeof(T) * pad_buffer_count(*p, sizeof(T))), "scratch (padded volume)");
     if (rc) return rc;
     const size_t np = project_partials_count(*p);
     if (sumsq) {
@@ -503,7 +504,7 @@ extern "C" int cbct_plan_lambda(const cbct_plan *p, int32_t n_iter, double *lamb
         int rc = check_hip(x.alloc(sizeof(float) * nvox), "scratch");
         if (!rc) rc = check_hip(y.alloc(sizeof(float) * nmeas), "scratch");
         if (!rc) rc = check_hip(w.alloc(sizeof(float) * nvox), "scratch");
-        if (!rc) rc = check_hip(pad.alloc(sizeof(float) * padded_of(p->g)), "scratch");
+        if (!rc) rc = check_hip(pad.alloc(sizeof(float) * pad_buffer_count(*p, sizeof(float))), "scratch");
         if (!rc) rc = check_hip(cells.alloc(sizeof(float) * cells_count(*p)), "scratch");
         if (!rc) rc = check_hip(part.alloc(sizeof(double) * 4096), "scratch");
         if (!rc) rc = check_hip(sc.alloc(sizeof(double)), "scratch");
@@ -611,7 +612,7 @@ int validate_params(const cbct_geom &g, const cbct_fbs_params *prm) {
 
 size_t level_bytes(const cbct_geom &g, bool own_yf) {
     const size_t nvox = nvox_of(g), nmeas = nmeas_of(g);
-    size_t b = sizeof(float) * (2 * nvox + nmeas + padded_of(g)) +
+    size_t b = sizeof(float) * (2 * nvox + nmeas + 2 * padded_of(g)) +
                sizeof(float) * 8 * (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
     if (own_yf) b += sizeof(float) * (nvox + nmeas);
     return b;
@@ -742,7 +743,7 @@ extern "C" int cbct_fbs_init(const cbct_plan *fine, const float *Y, float *f,
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.g, sizeof(float) * L.nvox, s);
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.z, sizeof(float) * L.nvox, s);
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.r, sizeof(float) * L.nmeas, s);
-            if (!rc) rc = alloc_owned(st.get(), (void **)&L.pad, sizeof(float) * padded_of(p.g), s);
+            if (!rc) rc = alloc_owned(st.get(), (void **)&L.pad, sizeof(float) * pad_buffer_count(p, sizeof(float)), s);
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.cells, sizeof(float) * cells_count(p), s);
         }
         if (!rc && st->n_levels == 2) {

@@ -90,6 +90,9 @@ hipError_t launch_gather_cells(const cbct_plan &p, const T *cells, const T *f, d
 hipError_t launch_count_samples(const cbct_plan &p, unsigned long long *count, hipStream_t s);
 
 size_t project_partials_count(const cbct_plan &p);
+size_t padded_count(const cbct_plan &p);
+// elements of the buffer launch_pad fills (two layouts for float volumes)
+size_t pad_buffer_count(const cbct_plan &p, size_t elem_size);
 size_t cells_count(const cbct_plan &p);
 
 hipError_t launch_tv_sweep(const GridConst &gc, const float *z, const float *g, float *out,

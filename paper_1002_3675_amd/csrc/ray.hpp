@@ -50,6 +50,57 @@ __device__ __forceinline__ void ray_setup(const ViewConst &vc, const DetConst &d
     Q[2] = vc.Qd[2];
 }
 
+// ---------------------------------------------------------------------------
+// Sample cells and trilinear weights.
+//
+// Float data (the production path): the samples of a ray are grouped in
+// segments of SEG consecutive indices n (a global lattice, n_s = n & ~(SEG-1),
+// independent of where the ray enters the grid).  The segment origin
+// q(n_s) = Q + n_s D is evaluated in double and split into an integer cell
+// I and a float fraction f in [0, 1]; inside the segment
+//     l = fma(m, D_f, f),   m = n - n_s in [0, SEG),  D_f = (float)D,
+// cell = I + floor(l), weight = l - floor(l).  |l| stays below SEG |D| + 1,
+// so float keeps the position to ~2e-6 voxel, and the double work is paid
+// once per segment instead of once per sample.
+//
+// Double data (derivative checks): q = fma(n, D, Q) in double per sample.
+constexpr int SEG = 32;
+
+struct SegOrigin {
+    int I[3];
+    float f[3];
+};
+
+__device__ __forceinline__ SegOrigin seg_origin(const double Q[3], const double D[3], int ns) {
+#pragma clang fp contract(off)
+    SegOrigin o;
+    const double nd = (double)ns;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double q = __builtin_fma(nd, D[a], Q[a]);
+        const double fl = __builtin_floor(q);
+        o.I[a] = (int)fl;
+        o.f[a] = (float)(q - fl);
+    }
+    return o;
+}
+
+// Cell offset (relative to the segment's integer origin) and weight along
+// one axis for in-segment index m.
+__device__ __forceinline__ void seg_axis(float m, float Df, float f, int &dc, float &w) {
+#pragma clang fp contract(off)
+    const float l = __builtin_fmaf(m, Df, f);
+    const float fl = __builtin_floorf(l);
+    dc = (int)fl;
+    w = l - fl;
+}
+
+__device__ __forceinline__ void to_float3(const double D[3], float Df[3]) {
+    Df[0] = (float)D[0];
+    Df[1] = (float)D[1];
+    Df[2] = (float)D[2];
+}
+
 // Voxel-index coordinate of sample n along one axis.
 __device__ __forceinline__ float sample_coord(float n, float D, float Q) {
     return __builtin_fmaf(n, D, Q);
@@ -101,7 +152,7 @@ __device__ __forceinline__ bool axis_estimate(float Q, float D, float a, float &
         // v = 0 for the same pixel)
         return Q >= a - 1e-3f && Q < a + 1.0f + 1e-3f;
     }
-    const float inv = 1.0f / D;
+    const float inv = __builtin_amdgcn_rcpf(D);
     const float m = 1e-3f + 4e-6f * (fabsf(Q) + fabsf(a) + 1.0f) * fabsf(inv);
     const float t0 = (a - Q) * inv, t1 = (a + 1.0f - Q) * inv;
     lo = fminf(t0, t1) - m;

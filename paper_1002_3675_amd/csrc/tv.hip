@@ -3,10 +3,13 @@
 //
 // D_a z = (z[v + e_a] - z[v]) / h_a (zero at the last index of axis a) and
 // D^T p = sum_a ([i_a > 0] p_a[v - e_a] - [i_a < N_a - 1] p_a[v]) / h_a.
-// The update at v needs p = Dz/|Dz|_eps at v and at v - e_a, i.e. z at v,
-// its six face neighbours and the six points v - e_a + e_b.  The sweep is
-// HBM-bound (12 bytes per voxel: read z and g, write z); a wavefront covers
-// 64 consecutive x so every neighbour load is a coalesced row.
+// The update at v needs p = Dz/|Dz|_eps at v and at v - e_a.  The sweep is
+// HBM-bound (12 bytes per voxel: read z and g, write z).  A workgroup owns a
+// 32 x 8 column of voxels and marches a chunk of z planes: each plane of z
+// (with a one-voxel halo) is staged once in LDS, p is computed once per
+// position of the tile and its low halo, and p_z of the plane below stays
+// in a register, so every voxel costs one read of z and g, one write, and
+// one reciprocal square root.
 #include "cbct_internal.hpp"
 
 namespace cbct {
@@ -15,6 +18,7 @@ namespace {
 
 constexpr int TV_BX = 64;
 constexpr int TV_BY = 4;
+constexpr int ST_X = 32, ST_Y = 8, ST_Z = 16;  // sweep tile and z chunk
 
 struct TvArgs {
     int nx, ny, nz;
@@ -22,56 +26,79 @@ struct TvArgs {
     float eps2;
 };
 
-// p = D z / |D z|_eps at (i, j, k), all in-bounds indices.
-__device__ __forceinline__ void normalised_grad(const float *__restrict__ z, const TvArgs &a, int i,
-                                                int j, int k, long long v, float &px, float &py,
-                                                float &pz) {
-    const long long sx = 1, sy = a.nx, sz = (long long)a.nx * a.ny;
-    const float zc = z[v];
-    const float gx = (i < a.nx - 1) ? (z[v + sx] - zc) * a.ihx : 0.0f;
-    const float gy = (j < a.ny - 1) ? (z[v + sy] - zc) * a.ihy : 0.0f;
-    const float gz = (k < a.nz - 1) ? (z[v + sz] - zc) * a.ihz : 0.0f;
-    const float inv = __builtin_amdgcn_rsqf(gx * gx + gy * gy + gz * gz + a.eps2);
-    px = gx * inv;
-    py = gy * inv;
-    pz = gz * inv;
-}
-
+// One projected gradient step on a 32 x 8 x ST_Z block of voxels.
 __global__ __launch_bounds__(256) void k_tv_sweep(TvArgs a, const float *__restrict__ z,
                                                   const float *__restrict__ g,
                                                   float *__restrict__ out, float beta, float step,
                                                   int nonneg) {
-    const int i = blockIdx.x * TV_BX + threadIdx.x;
-    const int j = blockIdx.y * TV_BY + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= a.nx || j >= a.ny) return;
+    // z planes k and k+1 with a one-voxel halo on every side of the tile
+    __shared__ float zs[2][ST_Y + 2][ST_X + 2];
+    // p = Dz/|Dz|_eps of plane k at the tile and its low halo
+    __shared__ float ps[3][ST_Y + 1][ST_X + 1];
+    const int tid = threadIdx.x;
+    const int tx = tid & (ST_X - 1), ty = tid / ST_X;
+    const int i0 = blockIdx.x * ST_X, j0 = blockIdx.y * ST_Y;
+    const int k0 = blockIdx.z * ST_Z, k1 = min(k0 + ST_Z, a.nz);
+    const int i = i0 + tx, j = j0 + ty;
+    const bool own = i < a.nx && j < a.ny;
     const long long sy = a.nx, sz = (long long)a.nx * a.ny;
-    const long long v = i + sy * j + sz * k;
-    float px, py, pz;
-    normalised_grad(z, a, i, j, k, v, px, py, pz);
-    float div = 0.0f;
-    if (i < a.nx - 1) div -= px * a.ihx;
-    if (j < a.ny - 1) div -= py * a.ihy;
-    if (k < a.nz - 1) div -= pz * a.ihz;
-    if (i > 0) {
-        float qx, qy, qz;
-        normalised_grad(z, a, i - 1, j, k, v - 1, qx, qy, qz);
-        div += qx * a.ihx;
+
+    auto load_plane = [&](int k, int slot) {
+        for (int t = tid; t < (ST_Y + 2) * (ST_X + 2); t += 256) {
+            const int jj = t / (ST_X + 2), ii = t % (ST_X + 2);
+            const int gi = i0 - 1 + ii, gj = j0 - 1 + jj;
+            float v = 0.0f;
+            if (k < a.nz && gi >= 0 && gi < a.nx && gj >= 0 && gj < a.ny)
+                v = z[gi + sy * gj + sz * k];
+            zs[slot][jj][ii] = v;
+        }
+    };
+
+    // p_z of the plane below the chunk, for this lane's voxel
+    float pz_prev = 0.0f;
+    if (own && k0 > 0) {
+        const long long v = i + sy * j + sz * (k0 - 1);
+        const float zc = z[v];
+        const float gx = (i < a.nx - 1) ? (z[v + 1] - zc) * a.ihx : 0.0f;
+        const float gy = (j < a.ny - 1) ? (z[v + sy] - zc) * a.ihy : 0.0f;
+        const float gz = (z[v + sz] - zc) * a.ihz;  // k0 - 1 < nz - 1
+        pz_prev = gz * __builtin_amdgcn_rsqf(gx * gx + gy * gy + gz * gz + a.eps2);
     }
-    if (j > 0) {
-        float qx, qy, qz;
-        normalised_grad(z, a, i, j - 1, k, v - sy, qx, qy, qz);
-        div += qy * a.ihy;
+    load_plane(k0, k0 & 1);
+    for (int k = k0; k < k1; ++k) {
+        const int A = k & 1, B = A ^ 1;
+        if (k + 1 < a.nz) load_plane(k + 1, B);
+        __syncthreads();
+        for (int t = tid; t < (ST_Y + 1) * (ST_X + 1); t += 256) {
+            const int jj = t / (ST_X + 1), ii = t % (ST_X + 1);
+            const int gi = i0 - 1 + ii, gj = j0 - 1 + jj;
+            const float zc = zs[A][jj][ii];
+            const float gx = (gi < a.nx - 1) ? (zs[A][jj][ii + 1] - zc) * a.ihx : 0.0f;
+            const float gy = (gj < a.ny - 1) ? (zs[A][jj + 1][ii] - zc) * a.ihy : 0.0f;
+            const float gz = (k < a.nz - 1) ? (zs[B][jj][ii] - zc) * a.ihz : 0.0f;
+            const float inv = __builtin_amdgcn_rsqf(gx * gx + gy * gy + gz * gz + a.eps2);
+            ps[0][jj][ii] = gx * inv;
+            ps[1][jj][ii] = gy * inv;
+            ps[2][jj][ii] = gz * inv;
+        }
+        const float zc = zs[A][ty + 1][tx + 1];
+        __syncthreads();
+        if (own) {
+            const float pz = ps[2][ty + 1][tx + 1];
+            float div = 0.0f;
+            if (i < a.nx - 1) div -= ps[0][ty + 1][tx + 1] * a.ihx;
+            if (j < a.ny - 1) div -= ps[1][ty + 1][tx + 1] * a.ihy;
+            if (k < a.nz - 1) div -= pz * a.ihz;
+            if (i > 0) div += ps[0][ty + 1][tx] * a.ihx;
+            if (j > 0) div += ps[1][ty][tx + 1] * a.ihy;
+            if (k > 0) div += pz_prev * a.ihz;
+            const long long v = i + sy * j + sz * k;
+            float zn = zc - step * (div + beta * (zc - g[v]));
+            if (nonneg) zn = fmaxf(zn, 0.0f);
+            out[v] = zn;
+            pz_prev = pz;
+        }
     }
-    if (k > 0) {
-        float qx, qy, qz;
-        normalised_grad(z, a, i, j, k - 1, v - sz, qx, qy, qz);
-        div += qz * a.ihz;
-    }
-    const float zc = z[v];
-    float zn = zc - step * (div + beta * (zc - g[v]));
-    if (nonneg) zn = fmaxf(zn, 0.0f);
-    out[v] = zn;
 }
 
 // Per-block partial sums of |Dz| and sqrt(|Dz|^2 + eps^2), in double.
@@ -131,7 +158,9 @@ dim3 tv_grid(const GridConst &gc) {
 
 hipError_t launch_tv_sweep(const GridConst &gc, const float *z, const float *g, float *out,
                            float beta, float eps, float step, int nonneg, hipStream_t s) {
-    hipLaunchKernelGGL(k_tv_sweep, tv_grid(gc), dim3(TV_BX, TV_BY), 0, s, args_of(gc, eps), z, g,
+    const dim3 grid((gc.nx + ST_X - 1) / ST_X, (gc.ny + ST_Y - 1) / ST_Y,
+                    (gc.nz + ST_Z - 1) / ST_Z);
+    hipLaunchKernelGGL(k_tv_sweep, grid, dim3(256), 0, s, args_of(gc, eps), z, g,
                        out, beta, step, nonneg);
     return hipGetLastError();
 }
