@@ -47,6 +47,13 @@ def parse():
     ap.add_argument("--cpu-views", type=int, default=4,
                     help="views of the head scan the CPU oracle sample uses")
     ap.add_argument("--ops-reps", type=int, default=10)
+    ap.add_argument("--serve-requests", type=int, default=12,
+                    help="requests in the served mixed stream (0 skips it)")
+    ap.add_argument("--lowdose", action="store_true",
+                    help="also run the 12-point low-dose quality sweep")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 256 MiB device copy first (the reference "
+                         "dispatch that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
 
 
@@ -100,6 +107,150 @@ def cpu_baseline(case_geom, Y, views):
                       % (views - 1, s, t1 - t0, t2 - t1)}
 
 
+def gpu_request_data(torch, cb, plan, g, seed, i0=5e4):
+    """Request input made on the device: a seeded random-ellipsoid head
+    voxelised at voxel centres, projected with the library's projector,
+    Poisson counts at I0, Y = ln(I0 / max(I, 1)).  Benchmark input only."""
+    import numpy as np
+    from workloads import random_ellipsoid_object
+    dev = plan.device
+    ph = random_ellipsoid_object(g, seed)
+    ax = [(torch.arange(n, device=dev, dtype=torch.float32) - (n - 1) / 2) * h
+          for n, h in ((g.nx, g.hx), (g.ny, g.hy), (g.nz, g.hz))]
+    zz, yy, xx = torch.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    f = torch.zeros(g.vol_shape, device=dev)
+    for e in ph:
+        r = torch.tensor(np.array(e.rot), dtype=torch.float32, device=dev)
+        d0, d1, d2 = xx - e.centre[0], yy - e.centre[1], zz - e.centre[2]
+        s = 0.0
+        for a in range(3):
+            b = (d0 * r[0, a] + d1 * r[1, a] + d2 * r[2, a]) / e.axes[a]
+            s = s + b * b
+        f += e.rho * (s <= 1.0).float()
+    p = plan.project(f.contiguous())
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    counts = torch.poisson(i0 * torch.exp(-p), generator=gen)
+    return torch.log(i0 / torch.clamp(counts, min=1.0)).contiguous()
+
+
+def serving_benchmark(torch, cb, n_req, seed=5000, load=0.8):
+    """Continuous batching of a Poisson stream of mixed requests versus the
+    same requests solved one at a time (FIFO) on the same GPU."""
+    import threading
+    import numpy as np
+    from workloads import serving_geometries
+    from paper_1002_3675_amd.serve import GpuExecutor, Request, Server
+    rng = np.random.default_rng(seed)
+    classes = serving_geometries()
+    names = sorted(classes)
+    ex = GpuExecutor(0)
+    reqs = []
+    t = time.perf_counter()
+    for k in range(n_req):
+        name = names[int(rng.integers(len(names)))]
+        g = classes[name].with_views(int(rng.choice([20, 30, 40, 60])))
+        plan = ex.plan_for(g)
+        Y = gpu_request_data(torch, cb, plan, g, seed + 1 + k)
+        reqs.append((name, g, Y))
+    params = cb.FbsParams(mu=1e-3, iters=(20, 20), eps=1e-3)
+    # one-at-a-time service times (the first solve of a geometry also pays
+    # its beta setup; warm every plan first so both runs see cached beta)
+    for _, g, Y in reqs:
+        cb.fbs_solve(ex.plan_for(g), Y, params)
+    torch.cuda.synchronize()
+    serial = []
+    for _, g, Y in reqs:
+        t0 = time.perf_counter()
+        cb.fbs_solve(ex.plan_for(g), Y, params)
+        torch.cuda.synchronize()
+        serial.append(time.perf_counter() - t0)
+    log("serving: %d requests made and timed alone in %.1f s" % (n_req, time.perf_counter() - t))
+    mean_s = float(np.mean(serial))
+    rate = load / mean_s
+    gaps = rng.exponential(1.0 / rate, size=n_req)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    # serial FIFO latencies for the same arrivals
+    done, lat_serial = 0.0, []
+    for a, s in zip(arrivals, serial):
+        start = max(a, done)
+        done = start + s
+        lat_serial.append(done - a)
+    serial_makespan = done
+    # the server in real time
+    budget = int(0.6 * torch.cuda.mem_get_info()[0])
+    srv = Server(ex, hbm_budget=budget, max_active=8, iters_per_tick=1)
+    srv.start()
+    futs = []
+    t0 = time.perf_counter()
+
+    def feed():
+        for (name, g, Y), a in zip(reqs, arrivals):
+            delay = t0 + a - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            futs.append(srv.submit(Request(g, Y, params, arrival=time.perf_counter())))
+
+    th = threading.Thread(target=feed)
+    th.start()
+    th.join()
+    res = [f.result(timeout=600) for f in futs]
+    srv.stop()
+    makespan = max(r.finished for r in res) - t0
+    lat = [r.latency for r in res]
+    return {
+        "requests": n_req,
+        "mix": {n: sum(1 for r in reqs if r[0] == n) for n in names},
+        "arrival_rate_per_s": rate,
+        "offered_load": load,
+        "served_p50_s": float(np.percentile(lat, 50)),
+        "served_p99_s": float(np.percentile(lat, 99)),
+        "served_throughput_req_s": n_req / makespan,
+        "serial_p50_s": float(np.percentile(lat_serial, 50)),
+        "serial_p99_s": float(np.percentile(lat_serial, 99)),
+        "serial_throughput_req_s": n_req / serial_makespan,
+        "mean_alone_solve_s": mean_s,
+        "peak_active": srv.peak_active,
+        "schedule": "20+20 iterations per request, 1 iteration per tick, up to 8 "
+                    "concurrent streams, admission by footprint",
+    }
+
+
+def lowdose_sweep(torch, cb):
+    """Head geometry, 20 and 30 views, I0 in {1e4, 2.5e4} with Gaussian
+    electronic noise (sigma 5 counts), mu in {5e-4, 1e-3, 2e-3}, 30 + 30
+    iterations: relative L2 error to the voxelised phantom over the grid and
+    over the field of view seen by every view."""
+    import numpy as np
+    from workloads import fov_mask, lowdose_case, voxelise
+    rows = []
+    truth = mask = None
+    for views in (20, 30):
+        for i0 in (1e4, 2.5e4):
+            case = lowdose_case(views, i0, 1e-3)
+            if truth is None:
+                truth = voxelise(case.geom, case.phantom, sub=2)
+                mask = fov_mask(case.geom)
+            plan = cb.Plan(case.geom)
+            Y = torch.as_tensor(case.Y, dtype=torch.float32, device="cuda")
+            for mu in (5e-4, 1e-3, 2e-3):
+                p = cb.FbsParams(mu=mu, iters=(30, 30), eps=1e-3, trace_energy=True)
+                cb.fbs_solve(plan, Y, p)  # beta setup for this data size
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                f, rep = cb.fbs_solve(plan, Y, p)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                fn = f.cpu().double().numpy()
+                err = np.linalg.norm(fn - truth) / np.linalg.norm(truth)
+                err_fov = np.linalg.norm((fn - truth)[mask]) / np.linalg.norm(truth[mask])
+                rows.append({"views": views, "I0": i0, "mu": mu, "rel_l2": err,
+                             "rel_l2_fov": err_fov, "recon_s": dt, "E": rep.E})
+                log("lowdose views=%d I0=%g mu=%g rel %.4f fov %.4f %.2f s"
+                    % (views, i0, mu, err, err_fov, dt))
+    return rows
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -117,6 +268,12 @@ def main():
         raise RuntimeError("bench.py needs a HIP device")
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        a = torch.ones(64 << 20, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     t = time.perf_counter()
     case = head_case(40, iters=(20, 20))
@@ -228,6 +385,12 @@ def main():
         "paper_context": "77-130 s per reconstruction on a Tesla C1060 (different "
                          "hardware, phantom and iteration count; not a target)",
     }
+    if args.lowdose:
+        out["lowdose"] = lowdose_sweep(torch, cb)
+    if args.serve_requests > 0:
+        t = time.perf_counter()
+        out["serving"] = serving_benchmark(torch, cb, args.serve_requests)
+        log("serving benchmark %.1f s" % (time.perf_counter() - t))
     if not args.no_cpu_baseline:
         t = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(g, case.Y, args.cpu_views)

@@ -17,16 +17,10 @@ namespace {
 constexpr int PROJ_BX = 64;
 constexpr int PROJ_BY = 4;
 
-// Zero-bordered copies of f: fp is [nz+2][ny+2][nx+2] (x fastest) and, when
-// fpt is not NULL, fpt is [nz+2][nx+2][ny+2] (y fastest).  Views whose rays
-// run mostly along x read fpt, so that the 64 lanes of a wavefront (64
-// neighbouring rays, spread across the rays' direction) still touch
-// consecutive addresses.  The transposed copy is written through a 32x32
-// LDS tile per xy slab so both copies are written with coalesced rows.
+// Zero-bordered copy of f: fp is [nz+2][ny+2][nx+2] (x fastest).
 template <typename T>
-__global__ __launch_bounds__(256) void k_pad(const T *__restrict__ f, T *__restrict__ fp,
-                                             T *__restrict__ fpt, int nx, int ny, int nz) {
-    __shared__ T tile[32][33];
+__global__ __launch_bounds__(256) void k_pad(const T *__restrict__ f, T *__restrict__ fp, int nx,
+                                             int ny, int nz) {
     const int px = nx + 2, py = ny + 2;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
     const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32, k = blockIdx.z;  // padded coords
@@ -37,13 +31,6 @@ __global__ __launch_bounds__(256) void k_pad(const T *__restrict__ f, T *__restr
         if (kin && i >= 1 && i <= nx && j >= 1 && j <= ny)
             v = f[(i - 1) + (long long)nx * ((j - 1) + (long long)ny * (k - 1))];
         if (i < px && j < py) fp[i + (long long)px * (j + (long long)py * k)] = v;
-        tile[r][tx] = v;
-    }
-    if (!fpt) return;
-    __syncthreads();
-    for (int r = ty; r < 32; r += 8) {
-        const int j = j0 + tx, i = i0 + r;  // y fastest
-        if (i < px && j < py) fpt[j + (long long)py * (i + (long long)px * k)] = tile[tx][r];
     }
 }
 
@@ -146,52 +133,6 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
-// Ray sum over [n0, n1] for float volumes: segment origins in double, the
-// per-sample cell and weights in float.  All lanes of the wavefront step
-// through the same sample index n (the union of their intervals, each lane
-// masked outside its own), so at every step the 64 neighbouring rays sit
-// at the same distance from the source and their taps share cache lines;
-// the loop bounds are wave-uniform.
-__device__ __forceinline__ double march_float(const double Q[3], const double D[3],
-                                              const float Df[3], int n0, int n1,
-                                              __amdgpu_buffer_rsrc_t vol, int px, int pxy) {
-    double acc = 0.0;
-    const bool any = n0 <= n1;
-    const int wlo = wave_min(any ? n0 : 0x7fffffff);
-    const int whi = wave_max(any ? n1 : -1);
-    for (int s = wlo & ~(SEG - 1); s <= whi; s += SEG) {
-        const SegOrigin o = seg_origin(Q, D, s);
-        const int base = (o.I[2] + 1) * pxy + (o.I[1] + 1) * px + (o.I[0] + 1);
-        const int ma = (wlo > s ? wlo : s) - s;
-        const int mb = (whi < s + SEG - 1 ? whi : s + SEG - 1) - s;
-        float seg = 0.0f;
-        float m = (float)ma;
-        for (int mi = ma; mi <= mb; ++mi, m += 1.0f) {
-            const int n = s + mi;
-            if (n < n0 || n > n1) continue;
-            int dx, dy, dz;
-            float wx, wy, wz;
-            seg_axis(m, Df[0], o.f[0], dx, wx);
-            seg_axis(m, Df[1], o.f[1], dy, wy);
-            seg_axis(m, Df[2], o.f[2], dz, wz);
-            const int off = 4 * (base + dx + __mul24(dy, px) + __mul24(dz, pxy));
-            const float2 a0 = load_pair(vol, off, 0);
-            const float2 a1 = load_pair(vol, off, 4 * px);
-            const float2 b0 = load_pair(vol, off, 4 * pxy);
-            const float2 b1 = load_pair(vol, off, 4 * (pxy + px));
-            const float c00 = a0.x + wx * (a0.y - a0.x);
-            const float c10 = a1.x + wx * (a1.y - a1.x);
-            const float c01 = b0.x + wx * (b0.y - b0.x);
-            const float c11 = b1.x + wx * (b1.y - b1.x);
-            const float c0 = c00 + wy * (c10 - c00);
-            const float c1 = c01 + wy * (c11 - c01);
-            seg += c0 + wz * (c1 - c0);
-        }
-        acc += (double)seg;
-    }
-    return acc;
-}
-
 // Ray sum for double volumes: double coordinates per sample.
 __device__ __forceinline__ double march_double(const double Q[3], const double D[3], int n0,
                                                int n1, const double *__restrict__ fp, int px,
@@ -217,11 +158,159 @@ __device__ __forceinline__ double march_double(const double Q[3], const double D
     return acc;
 }
 
+// ---------------------------------------------------------------------------
+// Float projector with LDS-staged volume.  A workgroup owns a 32 x 8 tile of
+// detector pixels of one view; its 256 rays advance together through
+// chunks of TILE_CH consecutive sample indices.  For each chunk the four
+// corner rays of the tile bound (with a margin for the curvature of the
+// ray bundle) the box of cells every sample of the chunk can touch; that box
+// of the zero-bordered volume is staged in LDS with row-coalesced loads and
+// the eight trilinear taps of every sample are read from LDS.  A chunk whose
+// box does not fit falls back to loads from global memory.  The samples,
+// their cells and weights are exactly those of march_float.
+constexpr int TILE_U = 32, TILE_V = 8, TILE_CH = 16;
+constexpr int TILE_LDS = 4096;  // floats
+
+__global__ __launch_bounds__(256) void k_project_tile(
+    const ViewConst *__restrict__ views, DetConst dc, GridConst gc, int nu, int nv,
+    const float *__restrict__ fp, int fp_elems, const float *__restrict__ Y,
+    float *__restrict__ out, double *__restrict__ partials, float step, int margin) {
+    __shared__ float vol[TILE_LDS];
+    __shared__ int red[2][4];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int i = blockIdx.x * TILE_U + (tid & (TILE_U - 1));
+    const int j = blockIdx.y * TILE_V + tid / TILE_U;
+    const int k = blockIdx.z;
+    const bool valid = i < nu && j < nv;
+    const ViewConst vc = views[k];
+    double Q[3], D[3];
+    float Df[3];
+    ray_setup(vc, dc, valid ? i : 0, valid ? j : 0, Q, D);
+    to_float3(D, Df);
+    int n0 = 1, n1 = 0;
+    if (valid) ray_interval<float>(Q, D, Df, gc, n0, n1);
+    // union of the tile's sample intervals
+    const bool any = n0 <= n1;
+    int lo = wave_min(any ? n0 : 0x7fffffff), hi = wave_max(any ? n1 : -1);
+    if (lane == 0) {
+        red[0][wid] = lo;
+        red[1][wid] = hi;
+    }
+    __syncthreads();
+    lo = min(min(red[0][0], red[0][1]), min(red[0][2], red[0][3]));
+    hi = max(max(red[1][0], red[1][1]), max(red[1][2], red[1][3]));
+    // corner rays of the tile (identical in every lane)
+    const int ci0 = blockIdx.x * TILE_U, ci1 = min(ci0 + TILE_U - 1, nu - 1);
+    const int cj0 = blockIdx.y * TILE_V, cj1 = min(cj0 + TILE_V - 1, nv - 1);
+    double Dc[4][3], Qc[3];
+    ray_setup(vc, dc, ci0, cj0, Qc, Dc[0]);
+    ray_setup(vc, dc, ci1, cj0, Qc, Dc[1]);
+    ray_setup(vc, dc, ci0, cj1, Qc, Dc[2]);
+    ray_setup(vc, dc, ci1, cj1, Qc, Dc[3]);
+    const int N[3] = {gc.nx, gc.ny, gc.nz};
+    const int px = gc.nx + 2, pxy = px * (gc.ny + 2);
+    const __amdgpu_buffer_rsrc_t gvol =
+        __builtin_amdgcn_make_buffer_rsrc((void *)fp, (short)0, fp_elems * 4, 0x00020000);
+    double acc = 0.0;
+    for (int nc = lo & ~(TILE_CH - 1); nc <= hi; nc += TILE_CH) {
+        // box of padded cells [b0, b1] per axis touched by this chunk
+        int b0[3], b1[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double qmin = 1e300, qmax = -1e300;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double qa = Qc[a] + (double)nc * Dc[c][a];
+                const double qb = Qc[a] + (double)(nc + TILE_CH - 1) * Dc[c][a];
+                qmin = fmin(qmin, fmin(qa, qb));
+                qmax = fmax(qmax, fmax(qa, qb));
+            }
+            // cells floor(q) in [-1, N-1] read padded indices cell+1 and cell+2
+            b0[a] = max((int)floor(fmax(qmin, -4.0)) - margin + 1, 0);
+            b1[a] = min((int)floor(fmin(qmax, (double)N[a] + 4.0)) + margin + 2, N[a] + 1);
+        }
+        const int RX = b1[0] - b0[0] + 1, RY = b1[1] - b0[1] + 1, RZ = b1[2] - b0[2] + 1;
+        const bool staged = RX > 0 && RY > 0 && RZ > 0 && RX * RY * RZ <= TILE_LDS;
+        __syncthreads();  // the previous chunk's readers are done
+        if (staged) {
+            for (int row = wid; row < RY * RZ; row += 4) {
+                const int ry = row % RY, rz = row / RY;
+                const int g = (b0[2] + rz) * pxy + (b0[1] + ry) * px + b0[0];
+                for (int x = lane; x < RX; x += 64)
+                    vol[row * RX + x] = __builtin_bit_cast(
+                        float, __builtin_amdgcn_raw_buffer_load_b32(gvol, (g + x) * 4, 0, 0));
+            }
+        }
+        __syncthreads();
+        const int na = max(n0, nc), nb = min(n1, nc + TILE_CH - 1);
+        if (na > nb) continue;
+        const int s = nc & ~(SEG - 1);
+        const SegOrigin o = seg_origin(Q, D, s);
+        float seg = 0.0f;
+        if (staged) {
+            const int RXY = RX * RY;
+            const int base = (o.I[2] + 1 - b0[2]) * RXY + (o.I[1] + 1 - b0[1]) * RX +
+                             (o.I[0] + 1 - b0[0]);
+            float m = (float)(na - s);
+            for (int n = na; n <= nb; ++n, m += 1.0f) {
+                int dx, dy, dz;
+                float wx, wy, wz;
+                seg_axis(m, Df[0], o.f[0], dx, wx);
+                seg_axis(m, Df[1], o.f[1], dy, wy);
+                seg_axis(m, Df[2], o.f[2], dz, wz);
+                const float *p = vol + base + dx + __mul24(dy, RX) + __mul24(dz, RXY);
+                const float c00 = p[0] + wx * (p[1] - p[0]);
+                const float c10 = p[RX] + wx * (p[RX + 1] - p[RX]);
+                const float c01 = p[RXY] + wx * (p[RXY + 1] - p[RXY]);
+                const float c11 = p[RXY + RX] + wx * (p[RXY + RX + 1] - p[RXY + RX]);
+                const float c0 = c00 + wy * (c10 - c00);
+                const float c1 = c01 + wy * (c11 - c01);
+                seg += c0 + wz * (c1 - c0);
+            }
+        } else {
+            const int base = (o.I[2] + 1) * pxy + (o.I[1] + 1) * px + (o.I[0] + 1);
+            float m = (float)(na - s);
+            for (int n = na; n <= nb; ++n, m += 1.0f) {
+                int dx, dy, dz;
+                float wx, wy, wz;
+                seg_axis(m, Df[0], o.f[0], dx, wx);
+                seg_axis(m, Df[1], o.f[1], dy, wy);
+                seg_axis(m, Df[2], o.f[2], dz, wz);
+                const int off = 4 * (base + dx + __mul24(dy, px) + __mul24(dz, pxy));
+                const float2 a0 = load_pair(gvol, off, 0);
+                const float2 a1 = load_pair(gvol, off, 4 * px);
+                const float2 c0v = load_pair(gvol, off, 4 * pxy);
+                const float2 c1v = load_pair(gvol, off, 4 * (pxy + px));
+                const float c00 = a0.x + wx * (a0.y - a0.x);
+                const float c10 = a1.x + wx * (a1.y - a1.x);
+                const float c01 = c0v.x + wx * (c0v.y - c0v.x);
+                const float c11 = c1v.x + wx * (c1v.y - c1v.x);
+                const float c0 = c00 + wy * (c10 - c00);
+                const float c1 = c01 + wy * (c11 - c01);
+                seg += c0 + wz * (c1 - c0);
+            }
+        }
+        acc += (double)seg;
+    }
+    double sq = 0.0;
+    if (valid) {
+        const long long idx = ((long long)k * nv + j) * nu + i;
+        float val = (float)(acc * (double)step);
+        if (Y) val -= Y[idx];
+        out[idx] = val;
+        sq = (double)val * (double)val;
+    }
+    if (partials) {
+        const int blin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+        block_sum_store(sq, partials, blin);
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_project(const ViewConst *__restrict__ views, DetConst dc,
                                                  GridConst gc, int nu, int nv,
                                                  const T *__restrict__ fp,
-                                                 const T *__restrict__ fpt, int fp_elems,
                                                  const T *__restrict__ Y, T *__restrict__ out,
                                                  double *__restrict__ partials, T step) {
     const int i = blockIdx.x * PROJ_BX + threadIdx.x;
@@ -232,33 +321,12 @@ __global__ __launch_bounds__(256) void k_project(const ViewConst *__restrict__ v
     double Q[3], D[3];
     float Df[3];
     ray_setup(vc, dc, valid ? i : 0, valid ? j : 0, Q, D);
-    // rays mostly along x: march the y-fastest copy with x and y exchanged
-    // (the per-axis cell arithmetic is unchanged by the relabelling)
-    const bool swap = fpt != nullptr && fabsf(vc.sn) > fabsf(vc.cs);
-    if (swap) {
-        double t = Q[0];
-        Q[0] = Q[1];
-        Q[1] = t;
-        t = D[0];
-        D[0] = D[1];
-        D[1] = t;
-        const int ti = gc.nx;
-        gc.nx = gc.ny;
-        gc.ny = ti;
-    }
     to_float3(D, Df);
     int n0 = 1, n1 = 0;
     if (valid) ray_interval<T>(Q, D, Df, gc, n0, n1);
     const int px = gc.nx + 2;
     const int pxy = px * (gc.ny + 2);
-    double acc;
-    if constexpr (sizeof(T) == 4) {
-        const __amdgpu_buffer_rsrc_t vol = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(swap ? fpt : fp), (short)0, fp_elems * 4, 0x00020000);
-        acc = march_float(Q, D, Df, n0, n1, vol, px, pxy);
-    } else {
-        acc = march_double(Q, D, n0, n1, fp, px, pxy);
-    }
+    const double acc = march_double(Q, D, n0, n1, fp, px, pxy);
     double sq = 0.0;
     if (valid) {
         const long long idx = ((long long)k * nv + j) * nu + i;
@@ -297,28 +365,41 @@ dim3 project_grid(const cbct_plan &p) {
     return dim3((p.g.nu + PROJ_BX - 1) / PROJ_BX, (p.g.nv + PROJ_BY - 1) / PROJ_BY, p.g.n_views);
 }
 
+dim3 tile_grid(const cbct_plan &p) {
+    return dim3((p.g.nu + TILE_U - 1) / TILE_U, (p.g.nv + TILE_V - 1) / TILE_V, p.g.n_views);
+}
+
+// Cells of margin around the corner rays' box: the samples of rays inside a
+// tile deviate from the corner rays' hull by at most t (1 - cos a) ~ t a^2/2,
+// with a the tile's angular half-diagonal and t the largest sample distance.
+int tile_margin(const cbct_plan &p) {
+    const cbct_geom &g = p.g;
+    const double hd = sqrt(pow(0.5 * TILE_U * g.au, 2) + pow(0.5 * TILE_V * g.av, 2));
+    const double a = hd / g.sdd;
+    const double tmax = g.sad + sqrt(pow(0.5 * (g.nx + 2) * g.hx, 2) +
+                                     pow(0.5 * (g.ny + 2) * g.hy, 2) +
+                                     pow(0.5 * (g.nz + 2) * g.hz, 2));
+    const double bulge = tmax * 0.5 * a * a * 1.01 / std::min(g.hx, std::min(g.hy, g.hz));
+    return std::max(1, (int)ceil(bulge + 1e-3));
+}
+
 }  // namespace
 
 size_t project_partials_count(const cbct_plan &p) {
-    dim3 g = project_grid(p);
-    return (size_t)g.x * g.y * g.z;
+    const dim3 a = project_grid(p), b = tile_grid(p);
+    return std::max((size_t)a.x * a.y * a.z, (size_t)b.x * b.y * b.z);
 }
 
 size_t padded_count(const cbct_plan &p) {
     return (size_t)(p.g.nx + 2) * (p.g.ny + 2) * (p.g.nz + 2);
 }
 
-// fpad holds padded_count elements for the x-fastest copy; float volumes
-// get the y-fastest copy right after it (2 * padded_count in total).
-size_t pad_buffer_count(const cbct_plan &p, size_t elem_size) {
-    return elem_size == 4 ? 2 * padded_count(p) : padded_count(p);
-}
+size_t pad_buffer_count(const cbct_plan &p, size_t) { return padded_count(p); }
 
 template <typename T>
 hipError_t launch_pad(const cbct_plan &p, const T *f, T *fpad, hipStream_t s) {
     dim3 grid((p.g.nx + 2 + 31) / 32, (p.g.ny + 2 + 31) / 32, p.g.nz + 2);
-    T *fpt = sizeof(T) == 4 ? fpad + padded_count(p) : nullptr;
-    hipLaunchKernelGGL(k_pad<T>, grid, dim3(256), 0, s, f, fpad, fpt, p.g.nx, p.g.ny, p.g.nz);
+    hipLaunchKernelGGL(k_pad<T>, grid, dim3(256), 0, s, f, fpad, p.g.nx, p.g.ny, p.g.nz);
     return hipGetLastError();
 }
 
@@ -326,10 +407,15 @@ template <typename T>
 hipError_t launch_project(const cbct_plan &p, const T *fpad, const T *Y, T *out,
                           double *partials, hipStream_t s) {
     const long long elems = (long long)padded_count(p);
-    const T *fpt = sizeof(T) == 4 ? fpad + elems : nullptr;
-    hipLaunchKernelGGL(k_project<T>, project_grid(p), dim3(PROJ_BX, PROJ_BY), 0, s, p.d_views,
-                       p.det, p.grid, p.g.nu, p.g.nv, fpad, fpt, (int)elems, Y, out, partials,
-                       (T)p.g.step);
+    if constexpr (sizeof(T) == 4) {
+        hipLaunchKernelGGL(k_project_tile, tile_grid(p), dim3(256), 0, s, p.d_views, p.det,
+                           p.grid, p.g.nu, p.g.nv, fpad, (int)elems, Y, out, partials,
+                           (float)p.g.step, tile_margin(p));
+    } else {
+        hipLaunchKernelGGL(k_project<T>, project_grid(p), dim3(PROJ_BX, PROJ_BY), 0, s,
+                           p.d_views, p.det, p.grid, p.g.nu, p.g.nv, fpad, Y, out, partials,
+                           (T)p.g.step);
+    }
     return hipGetLastError();
 }
 

@@ -229,6 +229,8 @@ class GpuExecutor:
         torch = self.torch
         plan = self.plan_for(req.geom)
         stream = torch.cuda.Stream(device=self.device)
+        # inputs produced on the submitter's stream are ready before use
+        stream.wait_stream(torch.cuda.current_stream(self.device))
         with torch.cuda.device(self.device), torch.cuda.stream(stream):
             Y = torch.as_tensor(req.Y, dtype=torch.float32).to(self.device, non_blocking=True)
             Y = Y.contiguous()
