@@ -251,6 +251,34 @@ def lowdose_sweep(torch, cb):
     return rows
 
 
+def tiny_recon_times(torch, cb):
+    """Seconds per reconstruction of the 64^3 / 16-view workload (10
+    iterations, beta and inner count from the oracle's rule on both sides):
+    the FP64 oracle on the host cores and the GPU solve."""
+    import numpy as np
+    import oracle
+    from workloads import tiny_case
+    case = tiny_case()
+    g = case.geom
+    lam = oracle.power_lambda(g, 30)
+    beta = oracle.beta_rule(g, case.mu, lam)
+    k = oracle.default_inner(np.array([g.hx, g.hy, g.hz]), beta, case.eps)
+    t0 = time.perf_counter()
+    oracle.fbs_solve(g, case.Y, case.mu, [10], beta=[beta], eps=case.eps, n_inner=[k])
+    cpu_s = time.perf_counter() - t0
+    plan = cb.Plan(g)
+    Y = torch.as_tensor(case.Y, dtype=torch.float32, device="cuda")
+    p = cb.FbsParams(mu=case.mu, iters=(10,), beta=[beta], eps=case.eps, n_inner=[k])
+    cb.fbs_solve(plan, Y, p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        cb.fbs_solve(plan, Y, p)
+    torch.cuda.synchronize()
+    return {"cpu_oracle_s": cpu_s, "cpu_threads": oracle.threads(),
+            "gpu_s": (time.perf_counter() - t0) / 5, "n_inner": k}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -394,6 +422,7 @@ def main():
     if not args.no_cpu_baseline:
         t = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(g, case.Y, args.cpu_views)
+        out["tiny_recon_64cubed_16views"] = tiny_recon_times(torch, cb)
         log("cpu baseline %.1f s" % (time.perf_counter() - t))
     print(json.dumps(out), flush=True)
 

@@ -1,0 +1,69 @@
+"""Full-size gates: the head workload (512x512x70, 40 views, 512x384) with
+the full two-level 20 + 20 schedule against the FP64 oracle's solve stored
+by tests/golden/make_head_fbs.py (volume within 1e-3 relative L2 over 4096
+seeded voxels of the field of view, energy within 1e-4), and the power
+iteration that sets beta against the oracle's."""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import head_case, tiny_geometry
+
+from gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "head40_fbs.json")
+
+
+def test_head_full_schedule_matches_oracle():
+    torch = require_gpu()
+    if not os.path.exists(GOLDEN):
+        pytest.skip("golden oracle solve not generated (tests/golden/make_head_fbs.py)")
+    import paper_1002_3675_amd as cb
+    sys.path.insert(0, os.path.join(HERE, "golden"))
+    from make_head_fbs import sample_indices
+    want = json.load(open(GOLDEN))
+    case = head_case(40, iters=(20, 20))
+    g = case.geom
+    plan = cb.Plan(g)
+    Y = torch.as_tensor(case.Y.astype(np.float32), device="cuda")
+    f, rep = cb.fbs_solve(plan, Y, cb.FbsParams(mu=case.mu, iters=(20, 20), beta=want["beta"],
+                                               eps=case.eps, n_inner=want["n_inner"],
+                                               trace_energy=True))
+    got = f.cpu().double().numpy().ravel()[sample_indices(g)]
+    ref = np.array(want["samples"])
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err <= 1e-3, err
+    assert abs(rep.E - want["E"]) <= 1e-4 * abs(want["E"]), (rep.E, want["E"])
+    assert float(f.min()) >= 0.0
+
+
+def test_power_iteration_matches_oracle():
+    require_gpu()
+    import paper_1002_3675_amd as cb
+    g = tiny_geometry()
+    lam_gpu = cb.Plan(g).power_lambda(30)
+    lam_or = oracle.power_lambda(g, 30)
+    assert abs(lam_gpu - lam_or) <= 1e-5 * lam_or, (lam_gpu, lam_or)
+
+
+def test_automatic_beta_matches_oracle_rule():
+    torch = require_gpu()
+    import paper_1002_3675_amd as cb
+    from workloads import tiny_case
+    case = tiny_case()
+    g = case.geom
+    plan = cb.Plan(g)
+    _, rep = cb.fbs_solve(plan, torch.as_tensor(case.Y, dtype=torch.float32, device="cuda"),
+                          cb.FbsParams(mu=case.mu, iters=(1,), eps=case.eps))
+    want = oracle.beta_rule(g, case.mu, oracle.power_lambda(g, 30))
+    assert abs(rep.beta_used[0] - want) <= 1e-5 * want
+    assert rep.n_inner_used[0] == oracle.default_inner(np.array([g.hx, g.hy, g.hz]),
+                                                       rep.beta_used[0], case.eps)

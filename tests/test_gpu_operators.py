@@ -165,6 +165,17 @@ def test_head_size_backprojection_one_view():
     assert rel_l2(f, want) <= TOL, rel_l2(f, want)
 
 
+def test_diff_size_projection_matches_oracle():
+    """128^3, 60 views, 256x192 (the differentiation workload)."""
+    require_gpu()
+    g = diff_geometry()
+    plan = _plan(g)
+    rng = np.random.default_rng(20)
+    f = rng.uniform(0, 0.02, g.vol_shape).astype(np.float32).astype(np.float64)
+    y = to_np(plan.project(to_dev(f)))
+    assert rel_l2(y, oracle.project(g, f)) <= TOL
+
+
 def test_diff_size_transpose_matches_oracle():
     """128^3, 60 views, 256x192 (the differentiation workload)."""
     require_gpu()
