@@ -685,7 +685,7 @@ extern "C" size_t cbct_fbs_footprint(const cbct_geom *g, const cbct_fbs_params *
     b += level_bytes(*g, false);
     if (prm->n_levels == 2) b += level_bytes(coarse_geom(*g), true);
     // partials and scalars
-    dim3 pg((g->nu + 63) / 64, (g->nv + 3) / 4, g->n_views);
+    dim3 pg((g->nu + 31) / 32, (g->nv + 7) / 8, g->n_views);  // projector tile grid
     size_t np = std::max((size_t)pg.x * pg.y * pg.z,
                          (size_t)2 * ((g->nx + 63) / 64) * ((g->ny + 3) / 4) * g->nz);
     b += sizeof(double) * (np + 8);

@@ -151,23 +151,39 @@ __device__ __forceinline__ void cell_samples(T acc[8], T rv, const double Qd[3],
                                              const double D[3], int n0, int n1, int cx, int cy,
                                              int cz) {
     if constexpr (sizeof(T) == 4) {
+#pragma clang fp contract(off)
         float Df[3];
         to_float3(D, Df);
         int ns = n0 & ~(SEG - 1);
         SegOrigin o = seg_origin(Qd, D, ns);
-        for (int n = n0; n <= n1; ++n) {
-            if (n - ns >= SEG) {
+        // The projector puts sample m of the segment in cell I + floor(l) with
+        // l = fma(m, Df, f).  For the integer L = c - I, floor(l) == L exactly
+        // when L <= l < L + 1, and the weight l - floor(l) is then l - L.
+        float L[3], H[3];
+        auto bounds = [&]() {
+            L[0] = (float)(cx - o.I[0]);
+            L[1] = (float)(cy - o.I[1]);
+            L[2] = (float)(cz - o.I[2]);
+            H[0] = L[0] + 1.0f;
+            H[1] = L[1] + 1.0f;
+            H[2] = L[2] + 1.0f;
+        };
+        bounds();
+        float m = (float)(n0 - ns);
+        for (int n = n0; n <= n1; ++n, m += 1.0f) {
+            if (n == ns + SEG) {
                 ns += SEG;
+                m = 0.0f;
                 o = seg_origin(Qd, D, ns);
+                bounds();
             }
-            const float m = (float)(n - ns);
-            int dx, dy, dz;
-            float wx, wy, wz;
-            seg_axis(m, Df[0], o.f[0], dx, wx);
-            seg_axis(m, Df[1], o.f[1], dy, wy);
-            seg_axis(m, Df[2], o.f[2], dz, wz);
-            if (o.I[0] + dx != cx || o.I[1] + dy != cy || o.I[2] + dz != cz) continue;
-            add_corners<T>(acc, rv, wx, wy, wz);
+            const float lx = __builtin_fmaf(m, Df[0], o.f[0]);
+            const float ly = __builtin_fmaf(m, Df[1], o.f[1]);
+            const float lz = __builtin_fmaf(m, Df[2], o.f[2]);
+            const bool in = (lx >= L[0]) & (lx < H[0]) & (ly >= L[1]) & (ly < H[1]) &
+                            (lz >= L[2]) & (lz < H[2]);
+            if (!in) continue;
+            add_corners<T>(acc, rv, lx - L[0], ly - L[1], lz - L[2]);
         }
     } else {
         double nf = (double)n0;
@@ -253,36 +269,29 @@ __global__ __launch_bounds__(256) void k_cells(const ViewConst *__restrict__ vie
         const float Qf[3] = {vc.Q[0], vc.Q[1], vc.Q[2]};
         const CellRange cr = cell_range(Qf, cxf, cyf, czf);
         if (staged) {
-            // Two passes over the cell's pixels, in tiles of 4 rows x 8
-            // columns: first a bit mask of the pixels whose rays can have
-            // samples in the cell, then the exact samples of the set bits
-            // only, so the wavefront runs the sample path max(popcount)
-            // times rather than once per pixel of the rectangle.
-            for (int jc = j0; jc <= j1; jc += 4)
-            for (int ic = i0; ic <= i1; ic += 8) {
-                const int je = min(jc + 3, j1), ie = min(ic + 7, i1);
-                unsigned mask = 0u;
-                for (int j = jc; j <= je; ++j) {
-                    const PixelRay *row = table + (j - bj0) * bw - bi0;
-                    for (int i = ic; i <= ie; ++i) {
-                        const float inv[3] = {row[i].inv[0], row[i].inv[1], row[i].inv[2]};
-                        int n0, n1;
-                        if (candidates_inv(cr, inv, n0, n1)) mask |= 1u << ((j - jc) * 8 + i - ic);
-                    }
+            // (the cell's rectangle is nearly its exact footprint: almost
+            // every pixel visited has samples in the cell).  One flat loop
+            // over the rectangle: lanes with rectangles of different shapes
+            // then diverge only in the total pixel count.
+            const int w = i1 - i0 + 1, h = j1 - j0 + 1;
+            const int npix = (w > 0 && h > 0) ? w * h : 0;
+            int i = i0, j = j0;
+            const PixelRay *row = table + (j0 - bj0) * bw - bi0;
+            for (int q = 0; q < npix; ++q) {
+                const PixelRay &pr = row[i];
+                const int pi = i, pj = j;
+                if (++i > i1) {
+                    i = i0;
+                    ++j;
+                    row += bw;
                 }
-                while (mask) {
-                    const int t = __builtin_ctz(mask);
-                    mask &= mask - 1u;
-                    const int j = jc + (t >> 3), i = ic + (t & 7);
-                    const PixelRay &pr = table[(j - bj0) * bw + (i - bi0)];
-                    const float inv[3] = {pr.inv[0], pr.inv[1], pr.inv[2]};
-                    int n0, n1;
-                    candidates_inv(cr, inv, n0, n1);
-                    const double D[3] = {pr.D[0], pr.D[1], pr.D[2]};
-                    // double data: residual at full precision from memory
-                    const T rv = sizeof(T) == 8 ? rk[(long long)j * nu + i] : (T)pr.r;
-                    cell_samples<T>(acc, rv, vc.Qd, D, n0, n1, cx, cy, cz);
-                }
+                const float inv[3] = {pr.inv[0], pr.inv[1], pr.inv[2]};
+                int n0, n1;
+                if (!candidates_inv(cr, inv, n0, n1)) continue;
+                const double D[3] = {pr.D[0], pr.D[1], pr.D[2]};
+                // double data: residual at full precision from memory
+                const T rv = sizeof(T) == 8 ? rk[(long long)pj * nu + pi] : (T)pr.r;
+                cell_samples<T>(acc, rv, vc.Qd, D, n0, n1, cx, cy, cz);
             }
             continue;
         }

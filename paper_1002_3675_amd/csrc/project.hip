@@ -231,15 +231,25 @@ __global__ __launch_bounds__(256) void k_project_tile(
             b1[a] = min((int)floor(fmin(qmax, (double)N[a] + 4.0)) + margin + 2, N[a] + 1);
         }
         const int RX = b1[0] - b0[0] + 1, RY = b1[1] - b0[1] + 1, RZ = b1[2] - b0[2] + 1;
-        const bool staged = RX > 0 && RY > 0 && RZ > 0 && RX * RY * RZ <= TILE_LDS;
+        // LDS rows have an odd pitch, so rays spread across rows (views whose
+        // rays run along x) do not pile onto one bank
+        const int RXP = RX | 1;
+        const bool staged = RX > 0 && RY > 0 && RZ > 0 && RXP * RY * RZ <= TILE_LDS;
         __syncthreads();  // the previous chunk's readers are done
         if (staged) {
-            for (int row = wid; row < RY * RZ; row += 4) {
-                const int ry = row % RY, rz = row / RY;
-                const int g = (b0[2] + rz) * pxy + (b0[1] + ry) * px + b0[0];
-                for (int x = lane; x < RX; x += 64)
-                    vol[row * RX + x] = __builtin_bit_cast(
-                        float, __builtin_amdgcn_raw_buffer_load_b32(gvol, (g + x) * 4, 0, 0));
+            // element t -> (x, row) -> (y, z), by float reciprocals: exact for
+            // t < 2^13 since (t + 1/2)/pitch stays >= 1/(2 pitch) from an integer
+            const float ipx = 1.0f / (float)RXP, ipy = 1.0f / (float)RY;
+            const int g0 = b0[2] * pxy + b0[1] * px + b0[0];
+            for (int t = tid; t < RXP * RY * RZ; t += 256) {
+                const int row = (int)(((float)t + 0.5f) * ipx);
+                const int x = t - row * RXP;
+                const int rz = (int)(((float)row + 0.5f) * ipy);
+                const int ry = row - rz * RY;
+                if (x < RX)
+                    vol[t] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                           gvol, (g0 + rz * pxy + ry * px + x) * 4,
+                                                           0, 0));
             }
         }
         __syncthreads();
@@ -249,6 +259,7 @@ __global__ __launch_bounds__(256) void k_project_tile(
         const SegOrigin o = seg_origin(Q, D, s);
         float seg = 0.0f;
         if (staged) {
+            const int RX = RXP;  // row pitch in LDS
             const int RXY = RX * RY;
             const int base = (o.I[2] + 1 - b0[2]) * RXY + (o.I[1] + 1 - b0[1]) * RX +
                              (o.I[0] + 1 - b0[0]);
@@ -385,9 +396,11 @@ int tile_margin(const cbct_plan &p) {
 
 }  // namespace
 
+// Partial sums written by a float projection (one per workgroup of the
+// tile grid); the double projector takes no partials.
 size_t project_partials_count(const cbct_plan &p) {
-    const dim3 a = project_grid(p), b = tile_grid(p);
-    return std::max((size_t)a.x * a.y * a.z, (size_t)b.x * b.y * b.z);
+    const dim3 b = tile_grid(p);
+    return (size_t)b.x * b.y * b.z;
 }
 
 size_t padded_count(const cbct_plan &p) {
@@ -412,6 +425,7 @@ hipError_t launch_project(const cbct_plan &p, const T *fpad, const T *Y, T *out,
                            p.grid, p.g.nu, p.g.nv, fpad, (int)elems, Y, out, partials,
                            (float)p.g.step, tile_margin(p));
     } else {
+        if (partials) return hipErrorInvalidValue;  // no partial sums in double
         hipLaunchKernelGGL(k_project<T>, project_grid(p), dim3(PROJ_BX, PROJ_BY), 0, s,
                            p.d_views, p.det, p.grid, p.g.nu, p.g.nv, fpad, Y, out, partials,
                            (T)p.g.step);

@@ -168,4 +168,10 @@ __device__ __forceinline__ int clamp_to_int(T x) {
     return (int)x;
 }
 
+// Same for float with one median-of-three (finite inputs).
+template <>
+__device__ __forceinline__ int clamp_to_int<float>(float x) {
+    return (int)__builtin_amdgcn_fmed3f(x, -4.0f, (float)(1 << 24));
+}
+
 }  // namespace cbct
