@@ -38,6 +38,39 @@ FLOPS_PER_SAMPLE = 34.0
 TV_BYTES_PER_VOXEL = 12.0   # read z and g, write z
 
 
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "hbm_traffic_head_fbs.md")
+
+
+def source_hash(src):
+    """First 16 hex digits of sha256 over a kernel's source and the shared headers."""
+    import hashlib
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1002_3675_amd", "csrc")
+    h = hashlib.sha256()
+    for f in (src, "ray.hpp", "cbct_internal.hpp"):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, mix):
+    """HBM bytes per launch of `kernel` in the timed mix of levels, from the
+    FETCH_SIZE / WRITE_SIZE counter runs recorded in the profile summary, or
+    None when the summary is missing or the kernel's sources changed since."""
+    if mix is None or not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 6 and parts[0] == "traffic:" and parts[1] == kernel:
+                if source_hash(parts[2]) != parts[3]:
+                    return None
+                fine, coarse = float(parts[4]), float(parts[5])
+                n_c, n_f = mix
+                return (n_c * coarse + n_f * fine) / max(n_c + n_f, 1)
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,6 +383,13 @@ def main():
         "tv_sweep": ("hbm", TV_BYTES_PER_VOXEL * sweeps),
         "gather": ("hbm", 4.0 * (8 + 1 + 1) * (iters[0] * nvox_c + iters[1] * nvox_f)),
     }
+    # launches per level (coarse, fine) of each kernel in one solve
+    mix = {
+        "project": (iters[0] + 1, iters[1] + 1),
+        "cells": (iters[0], iters[1]),
+        "tv_sweep": (rep.n_inner_used[0] * iters[0], rep.n_inner_used[1] * iters[1]),
+        "gather": (iters[0], iters[1]),
+    }
     dom = max(ktimes, key=lambda k: ktimes[k][1])
     per_kernel = {k: {"launches": n // args.steps, "ms_per_step": tot / args.steps}
                   for k, (n, tot) in ktimes.items()}
@@ -363,12 +403,14 @@ def main():
             achieved = per_launch / (avg_ms * 1e-3) / 1e12
             roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
                         "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
-                        "traffic": None, "kernel": dom, "avg_launch_ms": avg_ms}
+                        "traffic": measured_traffic(dom, mix.get(dom)), "kernel": dom,
+                        "avg_launch_ms": avg_ms}
         else:
             achieved = per_launch / (avg_ms * 1e-3) / 1e9
             roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                         "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                        "traffic": None, "kernel": dom, "avg_launch_ms": avg_ms}
+                        "traffic": measured_traffic(dom, mix.get(dom)), "kernel": dom,
+                        "avg_launch_ms": avg_ms}
 
     # stand-alone operator throughput at the fine level
     fr = torch.rand(g.vol_shape, device=dev) * 0.02
