@@ -35,7 +35,7 @@ PEAK_ALU_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, non-pa
 # of the transpose's cell pass (coordinate FMAs, floors, fractions, the
 # trilinear weights and the accumulation; counted in the design doc)
 FLOPS_PER_SAMPLE = 34.0
-TV_BYTES_PER_VOXEL = 12.0   # read z and g, write z
+TV_BYTES_PER_VOXEL = 12.0   # per sweep: read z and g, write z
 
 
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
@@ -69,6 +69,24 @@ def measured_traffic(kernel, mix):
                 n_c, n_f = mix
                 return (n_c * coarse + n_f * fine) / max(n_c + n_f, 1)
     return None
+
+
+def operator_rooflines(g, samples, ms_p, ms_pt):
+    """P and P^T at the fine level against both ceilings: algorithmic HBM
+    bytes (P: read the volume, write the projections; P^T: read the
+    projections, write the volume) over HBM peak, and 34 flop per ray
+    sample over the ALU peak."""
+    vol_b = 4.0 * g.n_vox
+    proj_b = 4.0 * g.n_meas
+    out = {}
+    for name, ms in (("P", ms_p), ("PT", ms_pt)):
+        gbs = (vol_b + proj_b) / (ms * 1e-3) / 1e9
+        tfl = FLOPS_PER_SAMPLE * samples / (ms * 1e-3) / 1e12
+        out[name] = {"ms": ms, "grays": samples / (ms * 1e-3) / 1e9,
+                     "algorithmic_bytes": vol_b + proj_b, "hbm_gbs": gbs,
+                     "hbm_frac": gbs / PEAK_HBM_GBS, "alu_tflops": tfl,
+                     "alu_frac": tfl / PEAK_ALU_TFLOPS}
+    return out
 
 
 def parse():
@@ -376,7 +394,8 @@ def main():
 
     # per-kernel algorithmic work over the timed region
     nvox_f, nvox_c = g.n_vox, plan_c.geom.nx * plan_c.geom.ny * plan_c.geom.nz
-    sweeps = rep.n_inner_used[0] * iters[0] * nvox_c + rep.n_inner_used[1] * iters[1] * nvox_f
+    tv_launches = list(rep.n_inner_used)  # one launch per inner step
+    sweeps = tv_launches[0] * iters[0] * nvox_c + tv_launches[1] * iters[1] * nvox_f
     work = {
         "project": ("alu", FLOPS_PER_SAMPLE * ((iters[0] + 1) * s_c + (iters[1] + 1) * s_f)),
         "cells": ("alu", FLOPS_PER_SAMPLE * (iters[0] * s_c + iters[1] * s_f)),
@@ -387,7 +406,7 @@ def main():
     mix = {
         "project": (iters[0] + 1, iters[1] + 1),
         "cells": (iters[0], iters[1]),
-        "tv_sweep": (rep.n_inner_used[0] * iters[0], rep.n_inner_used[1] * iters[1]),
+        "tv_sweep": (tv_launches[0] * iters[0], tv_launches[1] * iters[1]),
         "gather": (iters[0], iters[1]),
     }
     dom = max(ktimes, key=lambda k: ktimes[k][1])
@@ -450,6 +469,7 @@ def main():
         "P_fine_grays": s_f / (ms_p * 1e-3) / 1e9,
         "PT_fine_ms": ms_pt,
         "PT_fine_grays": s_f / (ms_pt * 1e-3) / 1e9,
+        "operators_fine": operator_rooflines(g, s_f, ms_p, ms_pt),
         "per_kernel": per_kernel,
         "roofline": roofline,
         "paper_context": "77-130 s per reconstruction on a Tesla C1060 (different "

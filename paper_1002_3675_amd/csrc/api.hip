@@ -175,6 +175,7 @@ struct Scratch {
     ~Scratch() { (void)scratch_free(p, s); }
     template <typename T>
     T *as() const { return static_cast<T *>(p); }
+    void *get() const { return p; }
 };
 
 hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
@@ -194,6 +195,12 @@ int validate_geom(const cbct_geom *g) {
     // float volumes are addressed with 32-bit byte offsets
     if (padded * 4.0 > 2147483647.0) return set_error(CBCT_EINVAL, "grid too large");
     if ((double)g->nu * g->nv > 2.0e9) return set_error(CBCT_EINVAL, "detector too large");
+    // grid limits: views and padded planes index the third grid dimension of
+    // some launches, all projector tiles form one linear grid
+    if (g->n_views > 65535 || g->nz + 2 > 65535)
+        return set_error(CBCT_EINVAL, "more than 65535 views or planes");
+    if (std::ceil(g->nu / 32.0) * std::ceil(g->nv / 8.0) * g->n_views > 2147483647.0)
+        return set_error(CBCT_EINVAL, "too many detector tiles");
     if (g->angles)
         for (int k = 0; k < g->n_views; ++k)
             if (!isfinite(g->angles[k])) return set_error(CBCT_EINVAL, "non-finite angle");
@@ -352,12 +359,14 @@ template <typename T>
 int backproject_impl(const cbct_plan *p, const T *y, const T *f, double tau, T *out,
                      hipStream_t s) {
     if (!p || !y || !out) return set_error(CBCT_EINVAL, "NULL argument");
-    Scratch cells(s);
-    int rc = check_hip(cells.alloc(sizeof(T) * cells_count(*p)), "scratch (cells)");
+    Scratch ws(s);
+    int rc = check_hip(ws.alloc(bp_workspace_bytes(p->g, sizeof(T))), "scratch (transpose workspace)");
     if (rc) return rc;
-    rc = check_hip(timed(CBCT_KERNEL_CELLS, s, [&] { return launch_backproject_cells<T>(*p, y, cells.as<T>(), s); }), "cell kernel");
+    rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_bp_prepare(*p, ws.get(), sizeof(T), s); }), "ray table");
     if (rc) return rc;
-    return check_hip(timed(CBCT_KERNEL_GATHER, s, [&] { return launch_gather_cells<T>(*p, cells.as<T>(), f, tau, out, s); }), "gather kernel");
+    rc = check_hip(timed(CBCT_KERNEL_CELLS, s, [&] { return launch_backproject_cells<T>(*p, y, ws.get(), s); }), "cell kernel");
+    if (rc) return rc;
+    return check_hip(timed(CBCT_KERNEL_GATHER, s, [&] { return launch_gather_cells<T>(*p, ws.get(), f, tau, out, s); }), "gather kernel");
 }
 
 }  // namespace
@@ -505,12 +514,13 @@ extern "C" int cbct_plan_lambda(const cbct_plan *p, int32_t n_iter, double *lamb
         if (!rc) rc = check_hip(y.alloc(sizeof(float) * nmeas), "scratch");
         if (!rc) rc = check_hip(w.alloc(sizeof(float) * nvox), "scratch");
         if (!rc) rc = check_hip(pad.alloc(sizeof(float) * pad_buffer_count(*p, sizeof(float))), "scratch");
-        if (!rc) rc = check_hip(cells.alloc(sizeof(float) * cells_count(*p)), "scratch");
+        if (!rc) rc = check_hip(cells.alloc(bp_workspace_bytes(p->g, sizeof(float))), "scratch");
         if (!rc) rc = check_hip(part.alloc(sizeof(double) * 4096), "scratch");
         if (!rc) rc = check_hip(sc.alloc(sizeof(double)), "scratch");
         if (rc) return rc;
         rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_fill(x.as<float>(), nvox, (float)(1.0 / sqrt((double)nvox)), s); }),
                        "fill");
+        if (!rc) rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_bp_prepare(*p, cells.get(), sizeof(float), s); }), "ray table");
         for (int it = 0; !rc && it < n_iter; ++it) {
             rc = check_hip(timed(CBCT_KERNEL_PAD, s, [&] { return launch_pad<float>(*p, x.as<float>(), pad.as<float>(), s); }), "pad");
             if (!rc)
@@ -519,10 +529,10 @@ extern "C" int cbct_plan_lambda(const cbct_plan *p, int32_t n_iter, double *lamb
                                "project");
             if (!rc)
                 rc = check_hip(timed(CBCT_KERNEL_CELLS, s, [&] { return launch_backproject_cells<float>(*p, y.as<float>(),
-                                                               cells.as<float>(), s); }),
+                                                               cells.get(), s); }),
                                "cells");
             if (!rc)
-                rc = check_hip(timed(CBCT_KERNEL_GATHER, s, [&] { return launch_gather_cells<float>(*p, cells.as<float>(), nullptr, 0.0,
+                rc = check_hip(timed(CBCT_KERNEL_GATHER, s, [&] { return launch_gather_cells<float>(*p, cells.get(), nullptr, 0.0,
                                                           w.as<float>(), s); }),
                                "gather");
             int np = 0;
@@ -612,8 +622,8 @@ int validate_params(const cbct_geom &g, const cbct_fbs_params *prm) {
 
 size_t level_bytes(const cbct_geom &g, bool own_yf) {
     const size_t nvox = nvox_of(g), nmeas = nmeas_of(g);
-    size_t b = sizeof(float) * (2 * nvox + nmeas + 2 * padded_of(g)) +
-               sizeof(float) * 8 * (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+    size_t b = sizeof(float) * (2 * nvox + nmeas + padded_of(g)) +
+               bp_workspace_bytes(g, sizeof(float));
     if (own_yf) b += sizeof(float) * (nvox + nmeas);
     return b;
 }
@@ -744,7 +754,8 @@ extern "C" int cbct_fbs_init(const cbct_plan *fine, const float *Y, float *f,
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.z, sizeof(float) * L.nvox, s);
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.r, sizeof(float) * L.nmeas, s);
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.pad, sizeof(float) * pad_buffer_count(p, sizeof(float)), s);
-            if (!rc) rc = alloc_owned(st.get(), (void **)&L.cells, sizeof(float) * cells_count(p), s);
+            if (!rc) rc = alloc_owned(st.get(), (void **)&L.cells, bp_workspace_bytes(p.g, sizeof(float)), s);
+            if (!rc) rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_bp_prepare(p, L.cells, sizeof(float), s); }), "ray table");
         }
         if (!rc && st->n_levels == 2) {
             const cbct_geom &g = fine->g;

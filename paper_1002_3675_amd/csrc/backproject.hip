@@ -198,25 +198,101 @@ __device__ __forceinline__ void cell_samples(T acc[8], T rv, const double Qd[3],
     }
 }
 
+// Geometry-only preparation, once per plan and workspace:
+//   k_rays:        the increment D (double) and its float reciprocals of the
+//                  ray through every pixel of every view;
+//   k_brick_rects: for every view and brick, the pixel rectangle whose rays
+//                  can reach the brick (its staged footprint).
+__global__ __launch_bounds__(256) void k_rays(const ViewConst *__restrict__ views, DetConst dc,
+                                              int nu, int nv, PixelRay *__restrict__ rays) {
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int k = blockIdx.z;
+    if (i >= nu || j >= nv) return;
+    double Q[3], D[3];
+    ray_setup(views[k], dc, i, j, Q, D);
+    float Df[3];
+    to_float3(D, Df);
+    PixelRay e;
+    e.D[0] = D[0];
+    e.D[1] = D[1];
+    e.D[2] = D[2];
+    e.inv[0] = inv_or_huge(Df[0]);
+    e.inv[1] = inv_or_huge(Df[1]);
+    e.inv[2] = inv_or_huge(Df[2]);
+    e.r = 0.0f;
+    rays[((long long)k * nv + j) * nu + i] = e;
+}
+
+// First cell and the box (mm) of brick (bxi, byi, bzi); the last brick of an
+// axis ends at the grid's last cell.  Cells c_a run from -1 to N_a - 1.
+struct BrickBox {
+    int c0[3];
+    float lo[3], hi[3];
+};
+
+__device__ __forceinline__ BrickBox brick_box(const GridConst &gc, int bxi, int byi, int bzi) {
+    BrickBox b;
+    b.c0[0] = bxi * CB_X - 1;
+    b.c0[1] = byi * CB_Y - 1;
+    b.c0[2] = bzi * CB_Z - 1;
+    const int x1 = min(b.c0[0] + CB_X - 1, gc.nx - 1), y1 = min(b.c0[1] + CB_Y - 1, gc.ny - 1),
+              z1 = min(b.c0[2] + CB_Z - 1, gc.nz - 1);
+    b.lo[0] = gc.x0 + (float)b.c0[0] * gc.hx;
+    b.hi[0] = gc.x0 + (float)(x1 + 1) * gc.hx;
+    b.lo[1] = gc.y0 + (float)b.c0[1] * gc.hy;
+    b.hi[1] = gc.y0 + (float)(y1 + 1) * gc.hy;
+    b.lo[2] = gc.z0 + (float)b.c0[2] * gc.hz;
+    b.hi[2] = gc.z0 + (float)(z1 + 1) * gc.hz;
+    return b;
+}
+
+__global__ __launch_bounds__(256) void k_brick_rects(const ViewConst *__restrict__ views,
+                                                     DetConst dc, GridConst gc, int nu, int nv,
+                                                     int nbx, int nby, int nbz, int nviews,
+                                                     int4 *__restrict__ rects) {
+    const long long nb = (long long)nbx * nby * nbz;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nb * nviews) return;
+    const int k = (int)(t / nb);
+    const int b = (int)(t - (long long)k * nb);
+    const int bxi = b % nbx, byi = (b / nbx) % nby, bzi = b / (nbx * nby);
+    const BrickBox bb = brick_box(gc, bxi, byi, bzi);
+    float umin, umax, vmin, vmax;
+    box_footprint(views[k], dc.sdd, bb.lo[0], bb.hi[0], bb.lo[1], bb.hi[1], bb.lo[2], bb.hi[2],
+                  umin, umax, vmin, vmax);
+    int i0, i1, j0, j1;
+    pixel_range(dc, nu, nv, umin, umax, vmin, vmax, i0, i1, j0, j1);
+    rects[t] = make_int4(i0, i1, j0, j1);
+}
+
+// Accumulate the samples of ray pr (residual rv) that fall in the cell.
+template <typename T>
+__device__ __forceinline__ void visit_pixel(T acc[8], const CellRange &cr, const PixelRay &pr,
+                                            T rv, const double Qd[3], int cx, int cy, int cz) {
+    const float inv[3] = {pr.inv[0], pr.inv[1], pr.inv[2]};
+    int n0, n1;
+    if (!candidates_inv(cr, inv, n0, n1)) return;
+    const double D[3] = {pr.D[0], pr.D[1], pr.D[2]};
+    cell_samples<T>(acc, rv, Qd, D, n0, n1, cx, cy, cz);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_cells(const ViewConst *__restrict__ views, DetConst dc,
                                                GridConst gc, int nu, int nv, int nviews,
+                                               const PixelRay *__restrict__ rays,
+                                               const int4 *__restrict__ rects,
                                                const T *__restrict__ r, T *__restrict__ cells,
                                                T step) {
     __shared__ PixelRay table[TABLE];
     const int tid = threadIdx.x;
-    const int bx0 = blockIdx.x * CB_X - 1, by0 = blockIdx.y * CB_Y - 1,
-              bz0 = blockIdx.z * CB_Z - 1;  // first cell of the brick
-    const int cx = bx0 + (tid & (CB_X - 1));
-    const int cy = by0 + ((tid / CB_X) & (CB_Y - 1));
-    const int cz = bz0 + tid / (CB_X * CB_Y);
+    const int nb = gridDim.x * gridDim.y * gridDim.z;
+    const int brick = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const BrickBox bb = brick_box(gc, blockIdx.x, blockIdx.y, blockIdx.z);
+    const int cx = bb.c0[0] + (tid & (CB_X - 1));
+    const int cy = bb.c0[1] + ((tid / CB_X) & (CB_Y - 1));
+    const int cz = bb.c0[2] + tid / (CB_X * CB_Y);
     const bool valid = cx < gc.nx && cy < gc.ny && cz < gc.nz;
-    // brick box (cells up to the last one of the grid)
-    const int bx1 = min(bx0 + CB_X - 1, gc.nx - 1), by1 = min(by0 + CB_Y - 1, gc.ny - 1),
-              bz1 = min(bz0 + CB_Z - 1, gc.nz - 1);
-    const float Bxa = gc.x0 + (float)bx0 * gc.hx, Bxb = gc.x0 + (float)(bx1 + 1) * gc.hx;
-    const float Bya = gc.y0 + (float)by0 * gc.hy, Byb = gc.y0 + (float)(by1 + 1) * gc.hy;
-    const float Bza = gc.z0 + (float)bz0 * gc.hz, Bzb = gc.z0 + (float)(bz1 + 1) * gc.hz;
     // this lane's cell box (same expressions as the brick box, so shared
     // faces round identically)
     const float xa = gc.x0 + (float)cx * gc.hx, xb = gc.x0 + (float)(cx + 1) * gc.hx;
@@ -229,38 +305,38 @@ __global__ __launch_bounds__(256) void k_cells(const ViewConst *__restrict__ vie
 
     for (int k = 0; k < nviews; ++k) {
         const ViewConst vc = views[k];
-        const T *rk = r + (long long)k * nu * nv;
-        // workgroup footprint, identical in every lane
-        float umin, umax, vmin, vmax;
-        box_footprint(vc, dc.sdd, Bxa, Bxb, Bya, Byb, Bza, Bzb, umin, umax, vmin, vmax);
-        int bi0, bi1, bj0, bj1;
-        pixel_range(dc, nu, nv, umin, umax, vmin, vmax, bi0, bi1, bj0, bj1);
+        const long long vbase = (long long)k * nu * nv;
+        const T *rk = r + vbase;
+        const PixelRay *raysk = rays + vbase;
+        // the brick's footprint, identical in every lane
+        const int4 rect = rects[(long long)k * nb + brick];
+        const int bi0 = rect.x, bi1 = rect.y, bj0 = rect.z, bj1 = rect.w;
         const int bw = bi1 - bi0 + 1, bh = bj1 - bj0 + 1;
         if (bw <= 0 || bh <= 0) continue;  // uniform: the brick misses the detector
-        const bool staged = bw * bh <= TABLE;
+        // float T stages the footprint's rays and residuals in LDS; double
+        // reads the residual at full precision from memory
+        const bool staged = sizeof(T) == 4 && bw * bh <= TABLE;
         if (staged) {
             __syncthreads();  // readers of the previous view are done
+            // element t -> (row, col) by a float reciprocal: exact for
+            // t < 2^13, since (t + 1/2)/bw stays >= 1/(2 bw) from an integer
+            const float ibw = 1.0f / (float)bw;
             for (int t = tid; t < bw * bh; t += 256) {
-                const int j = bj0 + t / bw, i = bi0 + t % bw;
-                double Q[3], D[3];
-                ray_setup(vc, dc, i, j, Q, D);
-                float Df[3];
-                to_float3(D, Df);
-                table[t].D[0] = D[0];
-                table[t].D[1] = D[1];
-                table[t].D[2] = D[2];
-                table[t].inv[0] = inv_or_huge(Df[0]);
-                table[t].inv[1] = inv_or_huge(Df[1]);
-                table[t].inv[2] = inv_or_huge(Df[2]);
-                table[t].r = (float)rk[(long long)j * nu + i];
+                const int row = (int)(((float)t + 0.5f) * ibw);
+                const int col = t - row * bw;
+                const long long pix = (long long)(bj0 + row) * nu + (bi0 + col);
+                PixelRay e = raysk[pix];
+                e.r = (float)rk[pix];
+                table[t] = e;
             }
             __syncthreads();
         }
         if (!valid) continue;
+        float umin, umax, vmin, vmax;
         box_footprint(vc, dc.sdd, xa, xb, ya, yb, za, zb, umin, umax, vmin, vmax);
         int i0, i1, j0, j1;
         pixel_range(dc, nu, nv, umin, umax, vmin, vmax, i0, i1, j0, j1);
-        // the cell lies in the brick: keep its pixels inside the staged
+        // the cell lies in the brick: keep its pixels inside the brick's
         // rectangle (they differ at most by rounding, inside the margin)
         i0 = max(i0, bi0);
         i1 = min(i1, bi1);
@@ -268,47 +344,31 @@ __global__ __launch_bounds__(256) void k_cells(const ViewConst *__restrict__ vie
         j1 = min(j1, bj1);
         const float Qf[3] = {vc.Q[0], vc.Q[1], vc.Q[2]};
         const CellRange cr = cell_range(Qf, cxf, cyf, czf);
+        // One flat loop over the cell's rectangle (nearly its exact
+        // footprint): lanes with rectangles of different shapes then
+        // diverge only in the total pixel count.
+        const int w = i1 - i0 + 1, h = j1 - j0 + 1;
+        const int npix = (w > 0 && h > 0) ? w * h : 0;
+        int i = i0, j = j0;
         if (staged) {
-            // (the cell's rectangle is nearly its exact footprint: almost
-            // every pixel visited has samples in the cell).  One flat loop
-            // over the rectangle: lanes with rectangles of different shapes
-            // then diverge only in the total pixel count.
-            const int w = i1 - i0 + 1, h = j1 - j0 + 1;
-            const int npix = (w > 0 && h > 0) ? w * h : 0;
-            int i = i0, j = j0;
             const PixelRay *row = table + (j0 - bj0) * bw - bi0;
             for (int q = 0; q < npix; ++q) {
                 const PixelRay &pr = row[i];
-                const int pi = i, pj = j;
+                if (++i > i1) {
+                    i = i0;
+                    row += bw;
+                }
+                visit_pixel<T>(acc, cr, pr, (T)pr.r, vc.Qd, cx, cy, cz);
+            }
+        } else {
+            for (int q = 0; q < npix; ++q) {
+                const long long pix = (long long)j * nu + i;
                 if (++i > i1) {
                     i = i0;
                     ++j;
-                    row += bw;
                 }
-                const float inv[3] = {pr.inv[0], pr.inv[1], pr.inv[2]};
-                int n0, n1;
-                if (!candidates_inv(cr, inv, n0, n1)) continue;
-                const double D[3] = {pr.D[0], pr.D[1], pr.D[2]};
-                // double data: residual at full precision from memory
-                const T rv = sizeof(T) == 8 ? rk[(long long)pj * nu + pi] : (T)pr.r;
-                cell_samples<T>(acc, rv, vc.Qd, D, n0, n1, cx, cy, cz);
-            }
-            continue;
-        }
-        for (int j = j0; j <= j1; ++j) {
-            for (int i = i0; i <= i1; ++i) {
-                int n0, n1;
-                {
-                    double Qd[3], D[3];
-                    ray_setup(vc, dc, i, j, Qd, D);
-                    float Df[3];
-                    to_float3(D, Df);
-                    const float inv[3] = {inv_or_huge(Df[0]), inv_or_huge(Df[1]),
-                                          inv_or_huge(Df[2])};
-                    if (!candidates_inv(cr, inv, n0, n1)) continue;
-                    cell_samples<T>(acc, rk[(long long)j * nu + i], vc.Qd, D, n0, n1, cx, cy,
-                                    cz);
-                }
+                const PixelRay pr = raysk[pix];
+                visit_pixel<T>(acc, cr, pr, rk[pix], vc.Qd, cx, cy, cz);
             }
         }
     }
@@ -346,34 +406,73 @@ __global__ __launch_bounds__(256) void k_gather(GridConst gc, const T *__restric
 
 }  // namespace
 
-size_t cells_count(const cbct_plan &p) {
-    return (size_t)8 * (p.g.nx + 1) * (p.g.ny + 1) * (p.g.nz + 1);
+namespace {
+
+dim3 brick_grid(const cbct_geom &g) {
+    return dim3((g.nx + 1 + CB_X - 1) / CB_X, (g.ny + 1 + CB_Y - 1) / CB_Y,
+                (g.nz + 1 + CB_Z - 1) / CB_Z);
 }
 
-template <typename T>
-hipError_t launch_backproject_cells(const cbct_plan &p, const T *r, T *cells, hipStream_t s) {
-    dim3 grid((p.g.nx + 1 + CB_X - 1) / CB_X, (p.g.ny + 1 + CB_Y - 1) / CB_Y,
-              (p.g.nz + 1 + CB_Z - 1) / CB_Z);
-    hipLaunchKernelGGL(k_cells<T>, grid, dim3(256), 0, s, p.d_views, p.det, p.grid, p.g.nu,
-                       p.g.nv, p.g.n_views, r, cells, (T)p.g.step);
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct BpLayout {
+    size_t rays, rects, total;  // byte offsets; the cell sums start at 0
+};
+
+BpLayout bp_layout(const cbct_geom &g, size_t elem) {
+    const dim3 b = brick_grid(g);
+    BpLayout l;
+    l.rays = align256(elem * 8 * (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1));
+    l.rects = l.rays + align256(sizeof(PixelRay) * (size_t)g.n_views * g.nu * g.nv);
+    l.total = l.rects + sizeof(int4) * (size_t)b.x * b.y * b.z * g.n_views;
+    return l;
+}
+
+}  // namespace
+
+size_t bp_workspace_bytes(const cbct_geom &g, size_t elem) { return bp_layout(g, elem).total; }
+
+hipError_t launch_bp_prepare(const cbct_plan &p, void *ws, size_t elem, hipStream_t s) {
+    const BpLayout l = bp_layout(p.g, elem);
+    char *base = (char *)ws;
+    hipLaunchKernelGGL(k_rays, dim3((p.g.nu + 63) / 64, (p.g.nv + 3) / 4, p.g.n_views), dim3(256),
+                       0, s, p.d_views, p.det, p.g.nu, p.g.nv, (PixelRay *)(base + l.rays));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 b = brick_grid(p.g);
+    const long long n = (long long)b.x * b.y * b.z * p.g.n_views;
+    hipLaunchKernelGGL(k_brick_rects, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       p.d_views, p.det, p.grid, p.g.nu, p.g.nv, (int)b.x, (int)b.y, (int)b.z,
+                       p.g.n_views, (int4 *)(base + l.rects));
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_gather_cells(const cbct_plan &p, const T *cells, const T *f, double tau,
+hipError_t launch_backproject_cells(const cbct_plan &p, const T *r, void *ws, hipStream_t s) {
+    const BpLayout l = bp_layout(p.g, sizeof(T));
+    char *base = (char *)ws;
+    hipLaunchKernelGGL(k_cells<T>, brick_grid(p.g), dim3(256), 0, s, p.d_views, p.det, p.grid,
+                       p.g.nu, p.g.nv, p.g.n_views, (const PixelRay *)(base + l.rays),
+                       (const int4 *)(base + l.rects), r, (T *)ws, (T)p.g.step);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather_cells(const cbct_plan &p, const void *ws, const T *f, double tau,
                                T *out, hipStream_t s) {
     dim3 grid((p.g.nx + G_BX - 1) / G_BX, (p.g.ny + G_BY - 1) / G_BY, p.g.nz);
-    hipLaunchKernelGGL(k_gather<T>, grid, dim3(G_BX, G_BY), 0, s, p.grid, cells, f, (T)tau, out);
+    hipLaunchKernelGGL(k_gather<T>, grid, dim3(G_BX, G_BY), 0, s, p.grid, (const T *)ws, f,
+                       (T)tau, out);
     return hipGetLastError();
 }
 
-template hipError_t launch_backproject_cells<float>(const cbct_plan &, const float *, float *,
+template hipError_t launch_backproject_cells<float>(const cbct_plan &, const float *, void *,
                                                     hipStream_t);
-template hipError_t launch_backproject_cells<double>(const cbct_plan &, const double *, double *,
+template hipError_t launch_backproject_cells<double>(const cbct_plan &, const double *, void *,
                                                      hipStream_t);
-template hipError_t launch_gather_cells<float>(const cbct_plan &, const float *, const float *,
+template hipError_t launch_gather_cells<float>(const cbct_plan &, const void *, const float *,
                                                double, float *, hipStream_t);
-template hipError_t launch_gather_cells<double>(const cbct_plan &, const double *,
+template hipError_t launch_gather_cells<double>(const cbct_plan &, const void *,
                                                 const double *, double, double *, hipStream_t);
 
 }  // namespace cbct

@@ -33,6 +33,19 @@ struct ViewConst {
     double pad_;
 };
 
+// The dispatcher hands the workgroups of a launch to the 8 XCDs of the chip
+// in turn by linear id, and each XCD has its own L2.  xcd_tile(b, n) maps
+// linear workgroup id b of n to a tile id so that every XCD receives one
+// contiguous range of tiles: neighbouring tiles, which read overlapping data,
+// then share an L2.  It is a bijection of [0, n) whatever the dispatch order.
+constexpr int XCDS = 8;
+
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int q = n / XCDS, r = n % XCDS;
+    const int x = b % XCDS, i = b / XCDS;
+    return x * q + (x < r ? x : r) + i;
+}
+
 struct DetConst {
     float u0, au, v0, av;  // pixel centre u = u0 + i*au, v = v0 + j*av (mm)
     float sdd2;            // sdd^2
@@ -82,18 +95,23 @@ hipError_t launch_pad(const cbct_plan &p, const T *f, T *fpad, hipStream_t s);
 template <typename T>
 hipError_t launch_project(const cbct_plan &p, const T *fpad, const T *Y, T *out,
                           double *partials, hipStream_t s);
+// The transpose works in a workspace of bp_workspace_bytes(p, sizeof(T))
+// bytes: the cell corner sums (at offset 0), then a per-pixel ray table and
+// per-brick pixel rectangles, which depend on the geometry only and are
+// filled by launch_bp_prepare before the first launch_backproject_cells.
+size_t bp_workspace_bytes(const cbct_geom &g, size_t elem_size);
+hipError_t launch_bp_prepare(const cbct_plan &p, void *ws, size_t elem_size, hipStream_t s);
 template <typename T>
-hipError_t launch_backproject_cells(const cbct_plan &p, const T *r, T *cells, hipStream_t s);
+hipError_t launch_backproject_cells(const cbct_plan &p, const T *r, void *ws, hipStream_t s);
 template <typename T>
-hipError_t launch_gather_cells(const cbct_plan &p, const T *cells, const T *f, double tau,
+hipError_t launch_gather_cells(const cbct_plan &p, const void *ws, const T *f, double tau,
                                T *out, hipStream_t s);
 hipError_t launch_count_samples(const cbct_plan &p, unsigned long long *count, hipStream_t s);
 
 size_t project_partials_count(const cbct_plan &p);
 size_t padded_count(const cbct_plan &p);
-// elements of the buffer launch_pad fills (two layouts for float volumes)
+// elements of the buffer launch_pad fills
 size_t pad_buffer_count(const cbct_plan &p, size_t elem_size);
-size_t cells_count(const cbct_plan &p);
 
 hipError_t launch_tv_sweep(const GridConst &gc, const float *z, const float *g, float *out,
                            float beta, float eps, float step, int nonneg, hipStream_t s);

@@ -179,9 +179,13 @@ __global__ __launch_bounds__(256) void k_project_tile(
     __shared__ int red[2][4];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
-    const int i = blockIdx.x * TILE_U + (tid & (TILE_U - 1));
-    const int j = blockIdx.y * TILE_V + tid / TILE_U;
-    const int k = blockIdx.z;
+    // tiles u-fastest, then v, then view; contiguous per XCD, so the rays
+    // of neighbouring tiles stage overlapping bricks through one L2
+    const int ntu = (nu + TILE_U - 1) / TILE_U, ntv = (nv + TILE_V - 1) / TILE_V;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tu = tile % ntu, tv = (tile / ntu) % ntv, k = tile / (ntu * ntv);
+    const int i = tu * TILE_U + (tid & (TILE_U - 1));
+    const int j = tv * TILE_V + tid / TILE_U;
     const bool valid = i < nu && j < nv;
     const ViewConst vc = views[k];
     double Q[3], D[3];
@@ -201,8 +205,8 @@ __global__ __launch_bounds__(256) void k_project_tile(
     lo = min(min(red[0][0], red[0][1]), min(red[0][2], red[0][3]));
     hi = max(max(red[1][0], red[1][1]), max(red[1][2], red[1][3]));
     // corner rays of the tile (identical in every lane)
-    const int ci0 = blockIdx.x * TILE_U, ci1 = min(ci0 + TILE_U - 1, nu - 1);
-    const int cj0 = blockIdx.y * TILE_V, cj1 = min(cj0 + TILE_V - 1, nv - 1);
+    const int ci0 = tu * TILE_U, ci1 = min(ci0 + TILE_U - 1, nu - 1);
+    const int cj0 = tv * TILE_V, cj1 = min(cj0 + TILE_V - 1, nv - 1);
     double Dc[4][3], Qc[3];
     ray_setup(vc, dc, ci0, cj0, Qc, Dc[0]);
     ray_setup(vc, dc, ci1, cj0, Qc, Dc[1]);
@@ -261,16 +265,21 @@ __global__ __launch_bounds__(256) void k_project_tile(
         if (staged) {
             const int RX = RXP;  // row pitch in LDS
             const int RXY = RX * RY;
+            const float RXf = (float)RX, RXYf = (float)RXY;
             const int base = (o.I[2] + 1 - b0[2]) * RXY + (o.I[1] + 1 - b0[1]) * RX +
                              (o.I[0] + 1 - b0[0]);
             float m = (float)(na - s);
             for (int n = na; n <= nb; ++n, m += 1.0f) {
-                int dx, dy, dz;
-                float wx, wy, wz;
-                seg_axis(m, Df[0], o.f[0], dx, wx);
-                seg_axis(m, Df[1], o.f[1], dy, wy);
-                seg_axis(m, Df[2], o.f[2], dz, wz);
-                const float *p = vol + base + dx + __mul24(dy, RX) + __mul24(dz, RXY);
+                // seg_axis's coordinates and weights; the LDS offset of the
+                // floors is formed in float (exact: |offset| < 2^24)
+                const float lx = __builtin_fmaf(m, Df[0], o.f[0]);
+                const float ly = __builtin_fmaf(m, Df[1], o.f[1]);
+                const float lz = __builtin_fmaf(m, Df[2], o.f[2]);
+                const float fx = __builtin_floorf(lx), fy = __builtin_floorf(ly),
+                            fz = __builtin_floorf(lz);
+                const float wx = lx - fx, wy = ly - fy, wz = lz - fz;
+                const float *p =
+                    vol + base + (int)__builtin_fmaf(fz, RXYf, __builtin_fmaf(fy, RXf, fx));
                 const float c00 = p[0] + wx * (p[1] - p[0]);
                 const float c10 = p[RX] + wx * (p[RX + 1] - p[RX]);
                 const float c01 = p[RXY] + wx * (p[RXY + 1] - p[RXY]);
@@ -312,10 +321,7 @@ __global__ __launch_bounds__(256) void k_project_tile(
         out[idx] = val;
         sq = (double)val * (double)val;
     }
-    if (partials) {
-        const int blin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-        block_sum_store(sq, partials, blin);
-    }
+    if (partials) block_sum_store(sq, partials, tile);
 }
 
 template <typename T>
@@ -376,8 +382,10 @@ dim3 project_grid(const cbct_plan &p) {
     return dim3((p.g.nu + PROJ_BX - 1) / PROJ_BX, (p.g.nv + PROJ_BY - 1) / PROJ_BY, p.g.n_views);
 }
 
+// One-dimensional grid of all tiles of all views (see xcd_tile).
 dim3 tile_grid(const cbct_plan &p) {
-    return dim3((p.g.nu + TILE_U - 1) / TILE_U, (p.g.nv + TILE_V - 1) / TILE_V, p.g.n_views);
+    return dim3((unsigned)((p.g.nu + TILE_U - 1) / TILE_U) * ((p.g.nv + TILE_V - 1) / TILE_V) *
+                p.g.n_views);
 }
 
 // Cells of margin around the corner rays' box: the samples of rays inside a
@@ -399,8 +407,7 @@ int tile_margin(const cbct_plan &p) {
 // Partial sums written by a float projection (one per workgroup of the
 // tile grid); the double projector takes no partials.
 size_t project_partials_count(const cbct_plan &p) {
-    const dim3 b = tile_grid(p);
-    return (size_t)b.x * b.y * b.z;
+    return (size_t)tile_grid(p).x;
 }
 
 size_t padded_count(const cbct_plan &p) {

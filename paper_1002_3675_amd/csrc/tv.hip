@@ -26,7 +26,28 @@ struct TvArgs {
     float eps2;
 };
 
-// One projected gradient step on a 32 x 8 x ST_Z block of voxels.
+// Tiles of a sweep: 32 x 8 columns of the xy plane, numbered x-fastest,
+// then y, then chunk of ST_Z planes, in launch order.  (Neighbouring tiles
+// share halo lines in L2 more often when each XCD takes a contiguous range,
+// but the last, shorter chunks then all land on one XCD; measured, the
+// plain order is faster here.)
+struct SweepTile {
+    int i0, j0, k0, k1;
+};
+
+__device__ __forceinline__ SweepTile sweep_tile(const TvArgs &a, int b) {
+    const int ntx = (a.nx + ST_X - 1) / ST_X, nty = (a.ny + ST_Y - 1) / ST_Y;
+    const int bx = b % ntx, by = (b / ntx) % nty, bz = b / (ntx * nty);
+    SweepTile t;
+    t.i0 = bx * ST_X;
+    t.j0 = by * ST_Y;
+    t.k0 = bz * ST_Z;
+    t.k1 = min(t.k0 + ST_Z, a.nz);
+    return t;
+}
+
+// One projected gradient step on a 32 x 8 tile marching a chunk of planes.
+// Plane k + 2 is fetched into registers while plane k is processed.
 __global__ __launch_bounds__(256) void k_tv_sweep(TvArgs a, const float *__restrict__ z,
                                                   const float *__restrict__ g,
                                                   float *__restrict__ out, float beta, float step,
@@ -37,21 +58,34 @@ __global__ __launch_bounds__(256) void k_tv_sweep(TvArgs a, const float *__restr
     __shared__ float ps[3][ST_Y + 1][ST_X + 1];
     const int tid = threadIdx.x;
     const int tx = tid & (ST_X - 1), ty = tid / ST_X;
-    const int i0 = blockIdx.x * ST_X, j0 = blockIdx.y * ST_Y;
-    const int k0 = blockIdx.z * ST_Z, k1 = min(k0 + ST_Z, a.nz);
+    const SweepTile st = sweep_tile(a, blockIdx.x);
+    const int i0 = st.i0, j0 = st.j0, k0 = st.k0, k1 = st.k1;
     const int i = i0 + tx, j = j0 + ty;
     const bool own = i < a.nx && j < a.ny;
     const long long sy = a.nx, sz = (long long)a.nx * a.ny;
 
-    auto load_plane = [&](int k, int slot) {
-        for (int t = tid; t < (ST_Y + 2) * (ST_X + 2); t += 256) {
-            const int jj = t / (ST_X + 2), ii = t % (ST_X + 2);
-            const int gi = i0 - 1 + ii, gj = j0 - 1 + jj;
-            float v = 0.0f;
-            if (k < a.nz && gi >= 0 && gi < a.nx && gj >= 0 && gj < a.ny)
-                v = z[gi + sy * gj + sz * k];
-            zs[slot][jj][ii] = v;
-        }
+    // plane elements of this lane: t = tid and t = tid + 256 of the
+    // (ST_Y + 2) x (ST_X + 2) halo tile
+    constexpr int NP = (ST_Y + 2) * (ST_X + 2);
+    int off[2];
+    bool inb[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int t = tid + 256 * e;
+        const int jj = t / (ST_X + 2), ii = t % (ST_X + 2);
+        const int gi = i0 - 1 + ii, gj = j0 - 1 + jj;
+        inb[e] = t < NP && gi >= 0 && gi < a.nx && gj >= 0 && gj < a.ny;
+        off[e] = inb[e] ? gi + a.nx * gj : 0;
+    }
+    auto fetch = [&](int k, float r[2]) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) r[e] = (inb[e] && k < a.nz) ? z[off[e] + sz * k] : 0.0f;
+    };
+    auto put = [&](int slot, const float r[2]) {
+        float *zp = &zs[slot][0][0];
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+            if (tid + 256 * e < NP) zp[tid + 256 * e] = r[e];
     };
 
     // p_z of the plane below the chunk, for this lane's voxel
@@ -64,10 +98,16 @@ __global__ __launch_bounds__(256) void k_tv_sweep(TvArgs a, const float *__restr
         const float gz = (z[v + sz] - zc) * a.ihz;  // k0 - 1 < nz - 1
         pz_prev = gz * __builtin_amdgcn_rsqf(gx * gx + gy * gy + gz * gz + a.eps2);
     }
-    load_plane(k0, k0 & 1);
+    float nxt[2];
+    fetch(k0, nxt);
+    put(k0 & 1, nxt);
+    fetch(k0 + 1, nxt);
     for (int k = k0; k < k1; ++k) {
         const int A = k & 1, B = A ^ 1;
-        if (k + 1 < a.nz) load_plane(k + 1, B);
+        put(B, nxt);                       // plane k + 1
+        if (k + 2 < k1 + 1) fetch(k + 2, nxt);  // in flight during this plane
+        const long long v = i + sy * j + sz * k;
+        const float gv = own ? g[v] : 0.0f;
         __syncthreads();
         for (int t = tid; t < (ST_Y + 1) * (ST_X + 1); t += 256) {
             const int jj = t / (ST_X + 1), ii = t % (ST_X + 1);
@@ -92,8 +132,7 @@ __global__ __launch_bounds__(256) void k_tv_sweep(TvArgs a, const float *__restr
             if (i > 0) div += ps[0][ty + 1][tx] * a.ihx;
             if (j > 0) div += ps[1][ty][tx + 1] * a.ihy;
             if (k > 0) div += pz_prev * a.ihz;
-            const long long v = i + sy * j + sz * k;
-            float zn = zc - step * (div + beta * (zc - g[v]));
+            float zn = zc - step * (div + beta * (zc - gv));
             if (nonneg) zn = fmaxf(zn, 0.0f);
             out[v] = zn;
             pz_prev = pz;
@@ -158,9 +197,9 @@ dim3 tv_grid(const GridConst &gc) {
 
 hipError_t launch_tv_sweep(const GridConst &gc, const float *z, const float *g, float *out,
                            float beta, float eps, float step, int nonneg, hipStream_t s) {
-    const dim3 grid((gc.nx + ST_X - 1) / ST_X, (gc.ny + ST_Y - 1) / ST_Y,
-                    (gc.nz + ST_Z - 1) / ST_Z);
-    hipLaunchKernelGGL(k_tv_sweep, grid, dim3(256), 0, s, args_of(gc, eps), z, g,
+    const int grid = ((gc.nx + ST_X - 1) / ST_X) * ((gc.ny + ST_Y - 1) / ST_Y) *
+                     ((gc.nz + ST_Z - 1) / ST_Z);
+    hipLaunchKernelGGL(k_tv_sweep, dim3(grid), dim3(256), 0, s, args_of(gc, eps), z, g,
                        out, beta, step, nonneg);
     return hipGetLastError();
 }

@@ -38,6 +38,27 @@ def test_tv_prox_matches_oracle(shape, h):
         assert float(z.min()) >= 0.0
 
 
+@pytest.mark.parametrize("shape", [(21, 37, 45), (33, 17, 70), (1, 9, 40)])
+def test_tv_steps_compose(shape):
+    """k inner steps in one call equal k calls of one step, and the oracle;
+    the shapes cut tiles, z chunks (16 planes) and the borders."""
+    torch = require_gpu()
+    import paper_1002_3675_amd as cb
+    rng = np.random.default_rng(22)
+    g = to_dev(rng.uniform(-0.002, 0.02, shape))
+    z0 = to_dev(rng.uniform(0.0, 0.02, shape))
+    h = np.array([0.9, 1.1, 2.3])
+    for beta, k in [(40.0, 2), (600.0, 5)]:
+        many = cb.tv_prox(g, z0, h, beta, 1e-3, k)
+        z = z0
+        for _ in range(k):
+            z = cb.tv_prox(g, z, h, beta, 1e-3, 1)
+        assert torch.equal(many, z)
+        want = oracle.tv_prox(g.double().cpu().numpy(), z0.double().cpu().numpy(), h, beta,
+                              1e-3, k)
+        assert rel_l2(to_np(many), want) <= 1e-5
+
+
 def test_tv_energy_matches_oracle():
     require_gpu()
     import paper_1002_3675_amd as cb
