@@ -286,9 +286,13 @@ __global__ __launch_bounds__(256) void k_cells(const ViewConst *__restrict__ vie
                                                T step) {
     __shared__ PixelRay table[TABLE];
     const int tid = threadIdx.x;
-    const int nb = gridDim.x * gridDim.y * gridDim.z;
-    const int brick = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    const BrickBox bb = brick_box(gc, blockIdx.x, blockIdx.y, blockIdx.z);
+    // bricks x-fastest, then y, then z; each XCD takes one contiguous range,
+    // so the bricks resident on an XCD at a time are neighbours whose
+    // footprints (ray table rows) overlap in its L2
+    const int nbx = (gc.nx + 1 + CB_X - 1) / CB_X, nby = (gc.ny + 1 + CB_Y - 1) / CB_Y;
+    const int nb = gridDim.x;
+    const int brick = xcd_tile(blockIdx.x, nb);
+    const BrickBox bb = brick_box(gc, brick % nbx, (brick / nbx) % nby, brick / (nbx * nby));
     const int cx = bb.c0[0] + (tid & (CB_X - 1));
     const int cy = bb.c0[1] + ((tid / CB_X) & (CB_Y - 1));
     const int cz = bb.c0[2] + tid / (CB_X * CB_Y);
@@ -451,7 +455,8 @@ template <typename T>
 hipError_t launch_backproject_cells(const cbct_plan &p, const T *r, void *ws, hipStream_t s) {
     const BpLayout l = bp_layout(p.g, sizeof(T));
     char *base = (char *)ws;
-    hipLaunchKernelGGL(k_cells<T>, brick_grid(p.g), dim3(256), 0, s, p.d_views, p.det, p.grid,
+    const dim3 b = brick_grid(p.g);
+    hipLaunchKernelGGL(k_cells<T>, dim3(b.x * b.y * b.z), dim3(256), 0, s, p.d_views, p.det, p.grid,
                        p.g.nu, p.g.nv, p.g.n_views, (const PixelRay *)(base + l.rays),
                        (const int4 *)(base + l.rects), r, (T *)ws, (T)p.g.step);
     return hipGetLastError();

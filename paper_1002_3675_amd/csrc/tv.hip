@@ -26,18 +26,21 @@ struct TvArgs {
     float eps2;
 };
 
-// Tiles of a sweep: 32 x 8 columns of the xy plane, numbered x-fastest,
-// then y, then chunk of ST_Z planes, in launch order.  (Neighbouring tiles
-// share halo lines in L2 more often when each XCD takes a contiguous range,
-// but the last, shorter chunks then all land on one XCD; measured, the
-// plain order is faster here.)
+// Tiles of a sweep: 32 x 8 columns of the xy plane (x-fastest, then y) in
+// chunks of ST_Z planes, chunk-major in launch order.  Within a chunk each
+// XCD takes one contiguous range of columns (xcd_tile), so neighbouring
+// tiles share their halo lines in one L2.  The remap stays inside a chunk:
+// over the whole grid it would hand the last, shorter chunks to one XCD.
 struct SweepTile {
     int i0, j0, k0, k1;
 };
 
 __device__ __forceinline__ SweepTile sweep_tile(const TvArgs &a, int b) {
     const int ntx = (a.nx + ST_X - 1) / ST_X, nty = (a.ny + ST_Y - 1) / ST_Y;
-    const int bx = b % ntx, by = (b / ntx) % nty, bz = b / (ntx * nty);
+    const int tpc = ntx * nty;  // tiles per chunk
+    const int bz = b / tpc;
+    const int tin = xcd_tile(b - bz * tpc, tpc);
+    const int bx = tin % ntx, by = tin / ntx;
     SweepTile t;
     t.i0 = bx * ST_X;
     t.j0 = by * ST_Y;
