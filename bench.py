@@ -100,6 +100,9 @@ def parse():
     ap.add_argument("--ops-reps", type=int, default=10)
     ap.add_argument("--serve-requests", type=int, default=12,
                     help="requests in the served mixed stream (0 skips it)")
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="offered load of the served stream: arrival rate times the "
+                         "mean one-at-a-time service time")
     ap.add_argument("--lowdose", action="store_true",
                     help="also run the 12-point low-dose quality sweep")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -479,7 +482,7 @@ def main():
         out["lowdose"] = lowdose_sweep(torch, cb)
     if args.serve_requests > 0:
         t = time.perf_counter()
-        out["serving"] = serving_benchmark(torch, cb, args.serve_requests)
+        out["serving"] = serving_benchmark(torch, cb, args.serve_requests, load=args.serve_load)
         log("serving benchmark %.1f s" % (time.perf_counter() - t))
     if not args.no_cpu_baseline:
         t = time.perf_counter()

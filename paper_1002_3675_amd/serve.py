@@ -30,7 +30,7 @@ from typing import Any, Callable, Dict, List, Optional
 __all__ = ["Request", "Result", "Server", "GpuExecutor"]
 
 
-@dataclasses.dataclass
+@dataclasses.dataclass(eq=False)
 class Request:
     """One reconstruction: geometry (any object with the Geometry fields),
     projections Y ([n_views][nv][nu], numpy or torch), solver settings."""
@@ -55,7 +55,7 @@ class Result:
         return self.finished - self.arrival
 
 
-@dataclasses.dataclass
+@dataclasses.dataclass(eq=False)  # slots compare by identity (fields hold arrays)
 class _Slot:
     req: Request
     fut: Future
@@ -92,10 +92,14 @@ class Server:
         self._thread: Optional[threading.Thread] = None
         self.peak_used = 0
         self.peak_active = 0
+        self._broken: Optional[BaseException] = None
 
     # ---------------------------------------------------------------- API --
     def submit(self, req: Request) -> Future:
         fut: Future = Future()
+        if self._broken is not None:
+            fut.set_exception(RuntimeError("server loop failed: %r" % (self._broken,)))
+            return fut
         fp = int(self.ex.footprint(req))
         if fp <= 0 or fp > self.budget:
             fut.set_exception(ValueError(
@@ -148,10 +152,14 @@ class Server:
 
     def start(self, poll: float = 5e-4):
         def loop():
-            while not self._stop:
-                if not self.tick():
-                    self._wake.wait(poll)
-                    self._wake.clear()
+            try:
+                while not self._stop:
+                    if not self.tick():
+                        self._wake.wait(poll)
+                        self._wake.clear()
+            except BaseException as e:  # a scheduler fault: no caller waits forever
+                self._fail_all(e)
+                raise
         self._stop = False
         self._thread = threading.Thread(target=loop, name="cbct-serve", daemon=True)
         self._thread.start()
@@ -164,6 +172,24 @@ class Server:
             self._thread = None
 
     # ----------------------------------------------------------- internals --
+    def _fail_all(self, e: BaseException):
+        """Fail every pending and active request with e; stop accepting."""
+        with self._lock:
+            self._broken = e
+            pending, self._pending = list(self._pending), type(self._pending)()
+            active, self._active = list(self._active), []
+        for _, fut, _ in pending:
+            if not fut.done():
+                fut.set_exception(RuntimeError("server loop failed: %r" % (e,)))
+        for s in active:
+            try:
+                self.ex.abort(s.handle)
+            except Exception:
+                pass
+            if not s.fut.done():
+                s.fut.set_exception(RuntimeError("server loop failed: %r" % (e,)))
+        self._used = 0
+
     def _admit(self) -> bool:
         worked = False
         while True:
@@ -191,9 +217,11 @@ class Server:
             worked = True
 
     def _retire(self, s: _Slot):
-        if s in self._active:
-            self._active.remove(s)
-            self._used -= s.footprint
+        for i, a in enumerate(self._active):
+            if a is s:
+                del self._active[i]
+                self._used -= s.footprint
+                break
 
 
 class GpuExecutor:

@@ -133,3 +133,39 @@ def test_background_thread_drains():
         srv.stop()
     assert [r.id for r in res] == list(range(6))
     assert all(r.finished >= r.admitted >= r.arrival for r in res)
+
+
+def test_out_of_order_completion_with_array_payloads():
+    """A later, shorter request finishes first while earlier ones are still
+    active; requests carry arrays (whose == is elementwise), so the server
+    must track its slots by identity."""
+    import numpy as np
+    ex = FakeExecutor()
+    srv = Server(ex, hbm_budget=1000, max_active=4)
+    futs = []
+    for rid, iters in enumerate((9, 7, 2, 1, 5)):
+        r = Request(geom=None, Y=np.ones((3, 4, 5)), params={"fp": 10, "iters": iters},
+                    id=rid)
+        futs.append(srv.submit(r))
+    srv.run_until_idle(timeout=5)
+    assert [f.result().report["iters"] for f in futs] == [9, 7, 2, 1, 5]
+    assert srv.used_bytes == 0 and not ex.live
+
+
+@pytest.mark.filterwarnings("ignore::pytest.PytestUnhandledThreadExceptionWarning")
+def test_scheduler_fault_fails_every_request_instead_of_hanging():
+    """If the scheduling loop itself raises (not a request's own error), the
+    background thread fails every pending and active future and refuses new
+    ones, so no caller waits forever."""
+    class Broken(FakeExecutor):
+        def poll(self, h):
+            raise KeyboardInterrupt  # escapes the per-request isolation
+    srv = Server(Broken(), hbm_budget=1000, max_active=2)
+    futs = [srv.submit(_req(10, 3)) for _ in range(4)]
+    srv.start()
+    for f in futs:
+        with pytest.raises(RuntimeError, match="server loop failed"):
+            f.result(timeout=5)
+    with pytest.raises(RuntimeError, match="server loop failed"):
+        srv.submit(_req(10, 3)).result(timeout=1)
+    srv._thread.join(timeout=5)
