@@ -248,7 +248,7 @@ def serving_benchmark(torch, cb, n_req, seed=5000, load=0.8):
     th = threading.Thread(target=feed)
     th.start()
     th.join()
-    res = [f.result(timeout=600) for f in futs]
+    res = [f.result(timeout=120) for f in futs]
     srv.stop()
     makespan = max(r.finished for r in res) - t0
     lat = [r.latency for r in res]
