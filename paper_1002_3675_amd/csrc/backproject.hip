@@ -29,7 +29,7 @@ namespace cbct {
 namespace {
 
 constexpr int CB_X = 8, CB_Y = 8, CB_Z = 4;  // cells per workgroup
-constexpr int TABLE = 768;                    // pixels staged per view
+constexpr int TABLE = 640;                    // pixels staged per view
 constexpr int G_BX = 64, G_BY = 4;            // pass-2 block
 
 // Staged per pixel: the ray increment D in double (exact cell test), the
