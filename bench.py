@@ -473,6 +473,8 @@ def main():
         "PT_fine_ms": ms_pt,
         "PT_fine_grays": s_f / (ms_pt * 1e-3) / 1e9,
         "operators_fine": operator_rooflines(g, s_f, ms_p, ms_pt),
+        "alu_measured_tflops": {"fp32_fma": cb.probe_fma_rate(False),
+                                "fp64_fma": cb.probe_fma_rate(True)},
         "per_kernel": per_kernel,
         "roofline": roofline,
         "paper_context": "77-130 s per reconstruction on a Tesla C1060 (different "

@@ -209,6 +209,14 @@ size_t cbct_fbs_footprint(const cbct_geom *g, const cbct_fbs_params *prm);
 int cbct_kernel_timing(int32_t enable);
 int cbct_kernel_timing_read(int32_t kernel, int64_t *launches, double *total_ms);
 
+/* Diagnostics: sustained fused multiply-add rate of this device, the
+ * measured ceiling of the ALU-bound kernels.  Runs one kernel of
+ * independent non-packed FMA chains (no memory traffic in its loop) on
+ * `stream`, in float32 (fp64 = 0) or float64 (fp64 = 1), times it with HIP
+ * events and writes TFLOP/s (2 flop per FMA) to *tflops_host.  Allocates
+ * and frees a small output buffer; synchronises `stream`. */
+int cbct_probe_fma_rate(int32_t fp64, double *tflops_host, void *stream);
+
 const char *cbct_strerror(int code);
 const char *cbct_last_error(void);
 

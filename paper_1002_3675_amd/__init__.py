@@ -377,6 +377,17 @@ def kernel_times():
     return out
 
 
+def probe_fma_rate(fp64: bool = False) -> float:
+    """Sustained non-packed FMA rate of the current device in TFLOP/s
+    (float32, or float64 with fp64=True): the measured ALU ceiling."""
+    torch = _torch()
+    out = ctypes.c_double()
+    check(_native.lib().cbct_probe_fma_rate(int(bool(fp64)), ctypes.byref(out),
+                                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+          "cbct_probe_fma_rate")
+    return float(out.value)
+
+
 def footprint(geom, params: FbsParams) -> int:
     """Device bytes of a solve, including the caller's Y and f."""
     c, ang = _to_c(Geometry.of(geom))

@@ -74,6 +74,7 @@ SIGNATURES = {
     "cbct_kernel_timing": (ctypes.c_int, [_I32]),
     "cbct_kernel_timing_read": (ctypes.c_int, [_I32, ctypes.POINTER(ctypes.c_int64),
                                                ctypes.POINTER(_D)]),
+    "cbct_probe_fma_rate": (ctypes.c_int, [_I32, ctypes.POINTER(_D), _P]),
     "cbct_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "cbct_last_error": (ctypes.c_char_p, []),
 }

@@ -164,6 +164,39 @@ extern "C" int cbct_kernel_timing_read(int32_t kernel, int64_t *launches, double
     return CBCT_OK;
 }
 
+extern "C" int cbct_probe_fma_rate(int32_t fp64, double *tflops_host, void *stream) {
+    if (!tflops_host) return set_error(CBCT_EINVAL, "tflops_host is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = 0, ncu = 0;
+    int rc = check_hip(hipGetDevice(&dev), "device");
+    if (!rc) rc = check_hip(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+    if (rc) return rc;
+    const int blocks = std::max(ncu, 1) * 16, iters = 8192;
+    const size_t bytes = (size_t)blocks * 256 * (fp64 ? sizeof(double) : sizeof(float));
+    void *out = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    rc = check_hip(hipMalloc(&out, bytes), "probe buffer");
+    if (!rc) rc = check_hip(hipEventCreate(&a), "event");
+    if (!rc) rc = check_hip(hipEventCreate(&b), "event");
+    if (!rc) rc = check_hip(launch_probe_fma(fp64 != 0, out, blocks, iters, s), "probe warm-up");
+    const int reps = 5;
+    if (!rc) rc = check_hip(hipEventRecord(a, s), "event record");
+    for (int r = 0; !rc && r < reps; ++r)
+        rc = check_hip(launch_probe_fma(fp64 != 0, out, blocks, iters, s), "probe");
+    if (!rc) rc = check_hip(hipEventRecord(b, s), "event record");
+    if (!rc) rc = check_hip(hipEventSynchronize(b), "event sync");
+    float ms = 0.0f;
+    if (!rc) rc = check_hip(hipEventElapsedTime(&ms, a, b), "event time");
+    if (!rc) {
+        const double flop = (double)reps * blocks * 256.0 * iters * 8.0 * 2.0;
+        *tflops_host = flop / (ms * 1e-3) / 1e12;
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (out) (void)hipFree(out);
+    return rc;
+}
+
 namespace {
 
 // RAII holder for stream-ordered scratch.

@@ -124,6 +124,9 @@ size_t tv_energy_partials_count(const GridConst &gc);
 hipError_t launch_sumsq(const float *x, size_t n, double *partials, int *n_partials,
                         hipStream_t s);
 hipError_t launch_fill(float *x, size_t n, float v, hipStream_t s);
+// FMA-rate probe: blocks x 256 lanes, iters x 8 FMAs each, into out
+// (blocks x 256 elements of float, or of double when fp64)
+hipError_t launch_probe_fma(bool fp64, void *out, int blocks, int iters, hipStream_t s);
 hipError_t launch_scale(const float *x, size_t n, const double *denom, float *out,
                         hipStream_t s);
 hipError_t launch_bin_detector(const float *y, int nu, int nv, int nviews, float *out,

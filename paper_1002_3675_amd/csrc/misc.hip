@@ -147,6 +147,36 @@ hipError_t launch_reduce_sum(const double *partials, int n, double *out, int nco
     return hipGetLastError();
 }
 
+// Independent FMA chains per lane; the sum is stored so the chains stay live.
+__device__ __forceinline__ float fma_t(float x, float a, float b) { return __builtin_fmaf(x, a, b); }
+__device__ __forceinline__ double fma_t(double x, double a, double b) { return __builtin_fma(x, a, b); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_probe_fma(T *__restrict__ out, int iters, T a, T b) {
+    T x[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) x[c] = (T)(threadIdx.x + c);
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) x[c] = fma_t(x[c], a, b);
+    }
+    T sum = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) sum += x[c];
+    out[(long long)blockIdx.x * 256 + threadIdx.x] = sum;
+}
+
+// flop of one probe launch: blocks x 256 lanes x iters x 8 chains x 2
+hipError_t launch_probe_fma(bool fp64, void *out, int blocks, int iters, hipStream_t s) {
+    if (fp64)
+        hipLaunchKernelGGL(k_probe_fma<double>, dim3(blocks), dim3(256), 0, s, (double *)out,
+                           iters, 0.999, 0.001);
+    else
+        hipLaunchKernelGGL(k_probe_fma<float>, dim3(blocks), dim3(256), 0, s, (float *)out,
+                           iters, 0.999f, 0.001f);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(float *x, size_t n, float v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill, dim3(grid_for((long long)n)), dim3(256), 0, s, x, (long long)n, v);
     return hipGetLastError();
