@@ -187,6 +187,40 @@ def test_diff_size_transpose_matches_oracle():
     assert rel_l2(f, oracle.backproject(g, y)) <= TOL
 
 
+# Geometries that force each operator's fallback path.
+# P^T: 2 mm voxels seen through 0.2 mm pixels at magnification 1.5, so an
+# 8x8x4-cell brick covers ~120 x 60 detector pixels, far beyond the LDS ray
+# table (640 pixels): every brick reads its rays from the global ray table.
+PT_FALLBACK = Geometry(16, 16, 16, 2.0, 2.0, 2.0, 256, 256, 0.2, 0.2, 300.0, 450.0, 3,
+                       angles=(0.3, 1.9, 4.0))
+# P: 8 mm pixels over 1 mm voxels, so the rays of a 32 x 8 pixel tile fan
+# over ~170 x 40 voxels and no 16-sample chunk's box fits the 16 KB of LDS:
+# every tap is read from the bordered volume in global memory.
+P_FALLBACK = Geometry(48, 48, 48, 1.0, 1.0, 1.0, 24, 16, 8.0, 8.0, 300.0, 450.0, 3,
+                      angles=(0.2, 2.2, 4.5))
+
+
+@pytest.mark.parametrize("name,g", [("pt_fallback", PT_FALLBACK), ("p_fallback", P_FALLBACK)])
+def test_fallback_paths_match_oracle(name, g):
+    torch = require_gpu()
+    _log("fallback parity %s" % name)
+    rng = np.random.default_rng(12)
+    f = rng.uniform(0.0, 0.02, g.vol_shape)
+    y = rng.uniform(-1.0, 4.0, g.proj_shape)
+    p = _plan(g)
+    got_p = to_np(p.project(to_dev(f)))
+    want_p = oracle.project(g, f.astype(np.float32).astype(np.float64))
+    assert rel_l2(got_p, want_p) <= TOL, rel_l2(got_p, want_p)
+    got_t = to_np(p.backproject(to_dev(y)))
+    want_t = oracle.backproject(g, y.astype(np.float32).astype(np.float64))
+    assert rel_l2(got_t, want_t) <= TOL, rel_l2(got_t, want_t)
+    # the float32 dot test ties the two paths together
+    fd, yd = to_dev(f, torch.float64), to_dev(y, torch.float64)
+    lhs = float((p.project(fd.float()).double() * yd).sum())
+    rhs = float((fd * p.backproject(yd.float()).double()).sum())
+    assert abs(lhs - rhs) <= 2e-6 * max(abs(lhs), abs(rhs)), (lhs, rhs)
+
+
 def test_fma_rate_probe_is_plausible():
     """The measured ALU ceiling the rooflines cite: positive, and not above
     the published vector peaks (157.3 TFLOP/s float32 with packed math,
