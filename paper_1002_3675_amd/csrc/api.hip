@@ -371,7 +371,7 @@ int project_impl(const cbct_plan *p, const T *f, const T *Y, T *out, double *sum
                  hipStream_t s) {
     if (!p || !f || !out) return set_error(CBCT_EINVAL, "NULL argument");
     Scratch pad(s), part(s);
-    int rc = check_hip(pad.alloc(sizeof(T) * pad_buffer_count(*p, sizeof(T))), "scratch (padded volume)");
+    int rc = check_hip(pad.alloc(sizeof(T) * padded_count(*p)), "scratch (padded volume)");
     if (rc) return rc;
     const size_t np = project_partials_count(*p);
     if (sumsq) {
@@ -546,7 +546,7 @@ extern "C" int cbct_plan_lambda(const cbct_plan *p, int32_t n_iter, double *lamb
         int rc = check_hip(x.alloc(sizeof(float) * nvox), "scratch");
         if (!rc) rc = check_hip(y.alloc(sizeof(float) * nmeas), "scratch");
         if (!rc) rc = check_hip(w.alloc(sizeof(float) * nvox), "scratch");
-        if (!rc) rc = check_hip(pad.alloc(sizeof(float) * pad_buffer_count(*p, sizeof(float))), "scratch");
+        if (!rc) rc = check_hip(pad.alloc(sizeof(float) * padded_count(*p)), "scratch");
         if (!rc) rc = check_hip(cells.alloc(bp_workspace_bytes(p->g, sizeof(float))), "scratch");
         if (!rc) rc = check_hip(part.alloc(sizeof(double) * 4096), "scratch");
         if (!rc) rc = check_hip(sc.alloc(sizeof(double)), "scratch");
@@ -786,7 +786,7 @@ extern "C" int cbct_fbs_init(const cbct_plan *fine, const float *Y, float *f,
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.g, sizeof(float) * L.nvox, s);
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.z, sizeof(float) * L.nvox, s);
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.r, sizeof(float) * L.nmeas, s);
-            if (!rc) rc = alloc_owned(st.get(), (void **)&L.pad, sizeof(float) * pad_buffer_count(p, sizeof(float)), s);
+            if (!rc) rc = alloc_owned(st.get(), (void **)&L.pad, sizeof(float) * padded_count(p), s);
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.cells, bp_workspace_bytes(p.g, sizeof(float)), s);
             if (!rc) rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_bp_prepare(p, L.cells, sizeof(float), s); }), "ray table");
         }

@@ -110,8 +110,6 @@ hipError_t launch_count_samples(const cbct_plan &p, unsigned long long *count, h
 
 size_t project_partials_count(const cbct_plan &p);
 size_t padded_count(const cbct_plan &p);
-// elements of the buffer launch_pad fills
-size_t pad_buffer_count(const cbct_plan &p, size_t elem_size);
 
 hipError_t launch_tv_sweep(const GridConst &gc, const float *z, const float *g, float *out,
                            float beta, float eps, float step, int nonneg, hipStream_t s);

@@ -414,7 +414,6 @@ size_t padded_count(const cbct_plan &p) {
     return (size_t)(p.g.nx + 2) * (p.g.ny + 2) * (p.g.nz + 2);
 }
 
-size_t pad_buffer_count(const cbct_plan &p, size_t) { return padded_count(p); }
 
 template <typename T>
 hipError_t launch_pad(const cbct_plan &p, const T *f, T *fpad, hipStream_t s) {
