@@ -68,8 +68,11 @@ typedef struct cbct_plan cbct_plan;
 typedef struct cbct_fbs_state cbct_fbs_state;
 
 /* Create a plan: validates g (sizes > 0, spacings > 0, sdd > sad > 0,
- * the source outside the grid), uploads per-view constants, and counts
- * the ray samples S.  EINVAL / ENOMEM / EHIP on failure; *out untouched. */
+ * the source outside the grid; limits: grid dimensions <= 32000, at most
+ * 65535 views, a padded float volume below 2 GiB, and sample indices
+ * (sdd + half the grid diagonal) / step <= 8e6), uploads per-view
+ * constants, and counts the ray samples S.  EINVAL / ENOMEM / EHIP on
+ * failure; *out untouched. */
 int cbct_plan_create(const cbct_geom *g, cbct_plan **out);
 void cbct_plan_destroy(cbct_plan *p);
 

@@ -232,6 +232,9 @@ int validate_geom(const cbct_geom *g) {
     // some launches, all projector tiles form one linear grid
     if (g->n_views > 65535 || g->nz + 2 > 65535)
         return set_error(CBCT_EINVAL, "more than 65535 views or planes");
+    // the transpose stores cell indices and segment numbers as 16-bit integers
+    if (g->nx > 32000 || g->ny > 32000 || g->nz > 32000)
+        return set_error(CBCT_EINVAL, "grid dimension above 32000");
     if (std::ceil(g->nu / 32.0) * std::ceil(g->nv / 8.0) * g->n_views > 2147483647.0)
         return set_error(CBCT_EINVAL, "too many detector tiles");
     if (g->angles)
@@ -263,6 +266,12 @@ extern "C" int cbct_plan_create(const cbct_geom *gin, cbct_plan **out) {
         std::unique_ptr<cbct_plan> p(new cbct_plan());
         p->g = *gin;
         if (!(p->g.step > 0)) p->g.step = 0.5 * std::min(gin->hx, std::min(gin->hy, gin->hz));
+        // sample indices n = t / step reach (sdd + half the grid) / step
+        // (the detector lies beyond every voxel); keep them well inside the
+        // 16-bit segment numbers of the transpose (n < 32767 * 256)
+        if ((p->g.sdd + 0.5 * sqrt(pow(p->g.nx * p->g.hx, 2) + pow(p->g.ny * p->g.hy, 2) +
+                                   pow(p->g.nz * p->g.hz, 2))) / p->g.step > 8.0e6)
+            return set_error(CBCT_EINVAL, "step too small for the source distance");
         p->angles.resize(gin->n_views);
         for (int k = 0; k < gin->n_views; ++k)
             p->angles[k] = gin->angles ? gin->angles[k] : 2.0 * M_PI * k / gin->n_views;

@@ -32,14 +32,30 @@ namespace cbct {
 namespace {
 
 constexpr int CB_X = 8, CB_Y = 8, CB_Z = 4;  // cells per workgroup
-constexpr int TABLE = 640;                    // pixels staged per view
+constexpr int TABLE = 544;                    // pixels staged per view (26 KB)
 constexpr int G_BX = 64, G_BY = 4;            // pass-2 block
 
-// Staged per pixel: the ray increment D in double (exact cell test), the
-// reciprocal of its float rounding (range estimate; 1e30 stands for the
-// reciprocal of an exactly zero component) and the residual.
+// Ray table entry per pixel and view (prepared once): the ray increment D
+// in double (segment origins) and the reciprocals of its float rounding
+// (range estimates; 1e30 stands for the reciprocal of an exactly zero
+// component).
 struct PixelRay {
     double D[3];
+    float inv[3];
+    float pad;
+};
+
+// LDS entry per footprint pixel of the current view: the origin (I, f) of
+// the segment sq * SEG that holds the ray's first sample in the brick, as
+// the projector computes it; D_f = (float)D; the reciprocals; the residual.
+// Cells whose samples of this ray start in another segment compute that
+// segment's origin from the ray table.  48 bytes.  Grid dimensions below
+// 32000 keep I (within SEG/2 + 2 cells of the brick) in a short.
+struct StagedRay {
+    short I[3];
+    short sq;
+    float f[3];
+    float Df[3];
     float inv[3];
     float r;
 };
@@ -147,57 +163,56 @@ __device__ __forceinline__ void add_corners(T acc[8], T rv, T wx, T wy, T wz) {
     t = a11 * wx; acc[6] += a11 - t; acc[7] += t;
 }
 
-// Samples n0..n1 of the ray (Qd, D) that fall in cell (cx, cy, cz): the
-// projector's cell arithmetic decides membership.
-template <typename T>
-__device__ __forceinline__ void cell_samples(T acc[8], T rv, const double Qd[3],
-                                             const double D[3], int n0, int n1, int cx, int cy,
-                                             int cz) {
-    if constexpr (sizeof(T) == 4) {
+// Samples n0..n1 of a ray that fall in cell (cx, cy, cz), float data: o is
+// the origin of segment ns = n0 & ~(SEG - 1); a later segment's origin is
+// computed from the ray's double increment in the ray table (gray).  The
+// projector's own cell arithmetic decides membership.
+__device__ __forceinline__ void cell_samples_f(float acc[8], float rv, const double Qd[3],
+                                               const PixelRay *gray, SegOrigin o, int ns,
+                                               const float Df[3], int n0, int n1, int cx,
+                                               int cy, int cz) {
 #pragma clang fp contract(off)
-        float Df[3];
-        to_float3(D, Df);
-        int ns = n0 & ~(SEG - 1);
-        SegOrigin o = seg_origin(Qd, D, ns);
-        // The projector puts sample m of the segment in cell I + floor(l) with
-        // l = fma(m, Df, f).  For the integer L = c - I, floor(l) == L exactly
-        // when L <= l < L + 1, and the weight l - floor(l) is then l - L.
-        float L[3], H[3];
-        auto bounds = [&]() {
-            L[0] = (float)(cx - o.I[0]);
-            L[1] = (float)(cy - o.I[1]);
-            L[2] = (float)(cz - o.I[2]);
-            H[0] = L[0] + 1.0f;
-            H[1] = L[1] + 1.0f;
-            H[2] = L[2] + 1.0f;
-        };
-        bounds();
-        float m = (float)(n0 - ns);
-        for (int n = n0; n <= n1; ++n, m += 1.0f) {
-            if (n == ns + SEG) {
-                ns += SEG;
-                m = 0.0f;
-                o = seg_origin(Qd, D, ns);
-                bounds();
-            }
-            const float lx = __builtin_fmaf(m, Df[0], o.f[0]);
-            const float ly = __builtin_fmaf(m, Df[1], o.f[1]);
-            const float lz = __builtin_fmaf(m, Df[2], o.f[2]);
-            const bool in = (lx >= L[0]) & (lx < H[0]) & (ly >= L[1]) & (ly < H[1]) &
-                            (lz >= L[2]) & (lz < H[2]);
-            if (!in) continue;
-            add_corners<T>(acc, rv, lx - L[0], ly - L[1], lz - L[2]);
+    // The projector puts sample m of the segment in cell I + floor(l) with
+    // l = fma(m, Df, f), weight l - floor(l): the sample is in cell c when
+    // floor(l) == L = c - I on every axis, and its weight is then l - L.
+    float L[3];
+    auto bounds = [&]() {
+        L[0] = (float)(cx - o.I[0]);
+        L[1] = (float)(cy - o.I[1]);
+        L[2] = (float)(cz - o.I[2]);
+    };
+    bounds();
+    float m = (float)(n0 - ns);
+    for (int n = n0; n <= n1; ++n, m += 1.0f) {
+        if (n == ns + SEG) {
+            ns += SEG;
+            m = 0.0f;
+            const double D[3] = {gray->D[0], gray->D[1], gray->D[2]};
+            o = seg_origin(Qd, D, ns);
+            bounds();
         }
-    } else {
-        double nf = (double)n0;
-        for (int n = n0; n <= n1; ++n, nf += 1.0) {
-            const double q0 = sample_coord(nf, D[0], Qd[0]);
-            const double q1 = sample_coord(nf, D[1], Qd[1]);
-            const double q2 = sample_coord(nf, D[2], Qd[2]);
-            const double f0 = floor_t(q0), f1 = floor_t(q1), f2 = floor_t(q2);
-            if ((int)f0 != cx || (int)f1 != cy || (int)f2 != cz) continue;
-            add_corners<T>(acc, rv, (T)(q0 - f0), (T)(q1 - f1), (T)(q2 - f2));
-        }
+        const float lx = __builtin_fmaf(m, Df[0], o.f[0]);
+        const float ly = __builtin_fmaf(m, Df[1], o.f[1]);
+        const float lz = __builtin_fmaf(m, Df[2], o.f[2]);
+        const bool in = (__builtin_floorf(lx) == L[0]) & (__builtin_floorf(ly) == L[1]) &
+                        (__builtin_floorf(lz) == L[2]);
+        if (!in) continue;
+        add_corners<float>(acc, rv, lx - L[0], ly - L[1], lz - L[2]);
+    }
+}
+
+// The same for double data: every sample in double, no segments.
+__device__ __forceinline__ void cell_samples_d(double acc[8], double rv, const double Qd[3],
+                                               const double D[3], int n0, int n1, int cx,
+                                               int cy, int cz) {
+    double nf = (double)n0;
+    for (int n = n0; n <= n1; ++n, nf += 1.0) {
+        const double q0 = sample_coord(nf, D[0], Qd[0]);
+        const double q1 = sample_coord(nf, D[1], Qd[1]);
+        const double q2 = sample_coord(nf, D[2], Qd[2]);
+        const double f0 = floor_t(q0), f1 = floor_t(q1), f2 = floor_t(q2);
+        if ((int)f0 != cx || (int)f1 != cy || (int)f2 != cz) continue;
+        add_corners<double>(acc, rv, q0 - f0, q1 - f1, q2 - f2);
     }
 }
 
@@ -223,7 +238,7 @@ __global__ __launch_bounds__(256) void k_rays(const ViewConst *__restrict__ view
     e.inv[0] = inv_or_huge(Df[0]);
     e.inv[1] = inv_or_huge(Df[1]);
     e.inv[2] = inv_or_huge(Df[2]);
-    e.r = 0.0f;
+    e.pad = 0.0f;
     rays[((long long)k * nv + j) * nu + i] = e;
 }
 
@@ -269,25 +284,57 @@ __global__ __launch_bounds__(256) void k_brick_rects(const ViewConst *__restrict
     rects[t] = make_int4(i0, i1, j0, j1);
 }
 
-// Accumulate the samples of ray pr (residual rv) that fall in the cell.
-template <typename T>
-__device__ __forceinline__ void visit_pixel(T acc[8], const CellRange &cr, const PixelRay &pr,
-                                            T rv, const double Qd[3], int cx, int cy, int cz) {
-    const float inv[3] = {pr.inv[0], pr.inv[1], pr.inv[2]};
+// Accumulate the samples of one ray (residual rv) that fall in the cell:
+// from an LDS entry (float data) or from the ray table (either type).
+__device__ __forceinline__ void visit_staged(float acc[8], const CellRange &cr,
+                                             const StagedRay &e, const PixelRay *gray,
+                                             const double Qd[3], int cx, int cy, int cz) {
+    const float inv[3] = {e.inv[0], e.inv[1], e.inv[2]};
     int n0, n1;
     if (!candidates_inv(cr, inv, n0, n1)) return;
-    const double D[3] = {pr.D[0], pr.D[1], pr.D[2]};
-    cell_samples<T>(acc, rv, Qd, D, n0, n1, cx, cy, cz);
+    const int ns = n0 & ~(SEG - 1);
+    SegOrigin o;
+    if (ns == (int)e.sq * SEG) {
+        o.I[0] = e.I[0];
+        o.I[1] = e.I[1];
+        o.I[2] = e.I[2];
+        o.f[0] = e.f[0];
+        o.f[1] = e.f[1];
+        o.f[2] = e.f[2];
+    } else {
+        const double D[3] = {gray->D[0], gray->D[1], gray->D[2]};
+        o = seg_origin(Qd, D, ns);
+    }
+    const float Df[3] = {e.Df[0], e.Df[1], e.Df[2]};
+    cell_samples_f(acc, e.r, Qd, gray, o, ns, Df, n0, n1, cx, cy, cz);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_cells(const ViewConst *__restrict__ views, DetConst dc,
+__device__ __forceinline__ void visit_global(T acc[8], const CellRange &cr, const PixelRay *gray,
+                                             T rv, const double Qd[3], int cx, int cy, int cz) {
+    const float inv[3] = {gray->inv[0], gray->inv[1], gray->inv[2]};
+    int n0, n1;
+    if (!candidates_inv(cr, inv, n0, n1)) return;
+    const double D[3] = {gray->D[0], gray->D[1], gray->D[2]};
+    if constexpr (sizeof(T) == 4) {
+        const int ns = n0 & ~(SEG - 1);
+        float Df[3];
+        to_float3(D, Df);
+        cell_samples_f(acc, rv, Qd, gray, seg_origin(Qd, D, ns), ns, Df, n0, n1, cx, cy, cz);
+    } else {
+        cell_samples_d(acc, rv, Qd, D, n0, n1, cx, cy, cz);
+    }
+}
+
+// Six workgroups of 256 lanes per CU: at most 80 VGPRs and 26 KB of LDS.
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_cells(const ViewConst *__restrict__ views, DetConst dc,
                                                GridConst gc, int nu, int nv, int nviews,
                                                const PixelRay *__restrict__ rays,
                                                const int4 *__restrict__ rects,
                                                const T *__restrict__ r, T *__restrict__ cells,
                                                T step) {
-    __shared__ PixelRay table[TABLE];
+    __shared__ StagedRay table[TABLE];
     const int tid = threadIdx.x;
     // bricks x-fastest, then y, then z; each XCD takes one contiguous range,
     // so the bricks resident on an XCD at a time are neighbours whose
@@ -300,6 +347,10 @@ __global__ __launch_bounds__(256) void k_cells(const ViewConst *__restrict__ vie
     const int cy = bb.c0[1] + ((tid / CB_X) & (CB_Y - 1));
     const int cz = bb.c0[2] + tid / (CB_X * CB_Y);
     const bool valid = cx < gc.nx && cy < gc.ny && cz < gc.nz;
+    // the brick in index coordinates: cells c0 .. c1 cover [c0, c1 + 1)
+    const float blo[3] = {(float)bb.c0[0], (float)bb.c0[1], (float)bb.c0[2]};
+    const float bhi[3] = {(float)min(bb.c0[0] + CB_X, gc.nx), (float)min(bb.c0[1] + CB_Y, gc.ny),
+                          (float)min(bb.c0[2] + CB_Z, gc.nz)};
     // this lane's cell box (same expressions as the brick box, so shared
     // faces round identically)
     const float xa = gc.x0 + (float)cx * gc.hx, xb = gc.x0 + (float)(cx + 1) * gc.hx;
@@ -320,8 +371,8 @@ __global__ __launch_bounds__(256) void k_cells(const ViewConst *__restrict__ vie
         const int bi0 = rect.x, bi1 = rect.y, bj0 = rect.z, bj1 = rect.w;
         const int bw = bi1 - bi0 + 1, bh = bj1 - bj0 + 1;
         if (bw <= 0 || bh <= 0) continue;  // uniform: the brick misses the detector
-        // float T stages the footprint's rays and residuals in LDS; double
-        // reads the residual at full precision from memory
+        // float data stages the footprint in LDS; double reads the ray
+        // table and the residual at full precision from memory
         const bool staged = sizeof(T) == 4 && bw * bh <= TABLE;
         if (staged) {
             __syncthreads();  // readers of the previous view are done
@@ -332,7 +383,29 @@ __global__ __launch_bounds__(256) void k_cells(const ViewConst *__restrict__ vie
                 const int row = (int)(((float)t + 0.5f) * ibw);
                 const int col = t - row * bw;
                 const long long pix = (long long)(bj0 + row) * nu + (bi0 + col);
-                PixelRay e = raysk[pix];
+                const PixelRay g = raysk[pix];
+                // first sample of the ray in the brick (a float estimate:
+                // it only picks which segment origin to prepare)
+                float tin = -3.0e38f;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float t0 = (blo[a] - vc.Q[a]) * g.inv[a];
+                    const float t1 = (bhi[a] - vc.Q[a]) * g.inv[a];
+                    tin = fmaxf(tin, fminf(t0, t1));
+                }
+                const int sb = max(clamp_to_int(floor_t(tin)), 0) & ~(SEG - 1);
+                const SegOrigin o = seg_origin(vc.Qd, g.D, sb);
+                StagedRay e;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    e.I[a] = (short)o.I[a];
+                    e.f[a] = o.f[a];
+                    e.Df[a] = (float)g.D[a];
+                    e.inv[a] = g.inv[a];
+                }
+                // 32767 marks "no staged origin" (the plan bounds real
+                // sample indices below 32767 * SEG)
+                e.sq = (short)min(sb / SEG, 32767);
                 e.r = (float)rk[pix];
                 table[t] = e;
             }
@@ -357,26 +430,29 @@ __global__ __launch_bounds__(256) void k_cells(const ViewConst *__restrict__ vie
         const int w = i1 - i0 + 1, h = j1 - j0 + 1;
         const int npix = (w > 0 && h > 0) ? w * h : 0;
         int i = i0, j = j0;
-        if (staged) {
-            const PixelRay *row = table + (j0 - bj0) * bw - bi0;
-            for (int q = 0; q < npix; ++q) {
-                const PixelRay &pr = row[i];
-                if (++i > i1) {
-                    i = i0;
-                    row += bw;
+        if constexpr (sizeof(T) == 4) {
+            if (staged) {
+                const StagedRay *row = table + (j0 - bj0) * bw - bi0;
+                for (int q = 0; q < npix; ++q) {
+                    const StagedRay &e = row[i];
+                    const PixelRay *gray = raysk + (long long)j * nu + i;
+                    if (++i > i1) {
+                        i = i0;
+                        ++j;
+                        row += bw;
+                    }
+                    visit_staged(acc, cr, e, gray, vc.Qd, cx, cy, cz);
                 }
-                visit_pixel<T>(acc, cr, pr, (T)pr.r, vc.Qd, cx, cy, cz);
+                continue;
             }
-        } else {
-            for (int q = 0; q < npix; ++q) {
-                const long long pix = (long long)j * nu + i;
-                if (++i > i1) {
-                    i = i0;
-                    ++j;
-                }
-                const PixelRay pr = raysk[pix];
-                visit_pixel<T>(acc, cr, pr, rk[pix], vc.Qd, cx, cy, cz);
+        }
+        for (int q = 0; q < npix; ++q) {
+            const long long pix = (long long)j * nu + i;
+            if (++i > i1) {
+                i = i0;
+                ++j;
             }
+            visit_global<T>(acc, cr, raysk + pix, rk[pix], vc.Qd, cx, cy, cz);
         }
     }
     if (!valid) return;

@@ -59,12 +59,16 @@ __device__ __forceinline__ void ray_setup(const ViewConst &vc, const DetConst &d
 // q(n_s) = Q + n_s D is evaluated in double and split into an integer cell
 // I and a float fraction f in [0, 1]; inside the segment
 //     l = fma(m, D_f, f),   m = n - n_s in [0, SEG),  D_f = (float)D,
-// cell = I + floor(l), weight = l - floor(l).  |l| stays below SEG |D| + 1,
-// so float keeps the position to ~2e-6 voxel, and the double work is paid
-// once per segment instead of once per sample.
+// cell = I + floor(l), weight = l - floor(l).  With the default step
+// (|D_a| <= 1/2) |l| stays below SEG/2 + 1 = 129, so float keeps the
+// position to ~1.5e-5 voxel (one rounding of l plus the rounding of D_f
+// over 256 steps), and the double work is paid once per segment.  Long
+// segments matter to the transpose: the samples of one ray inside one
+// brick of cells (at most ~33 of them) nearly always share a segment,
+// whose origin can then be prepared once per pixel and brick.
 //
 // Double data (derivative checks): q = fma(n, D, Q) in double per sample.
-constexpr int SEG = 32;
+constexpr int SEG = 256;
 
 struct SegOrigin {
     int I[3];
