@@ -183,21 +183,26 @@ __device__ __forceinline__ void cell_samples_f(float acc[8], float rv, const dou
     };
     bounds();
     float m = (float)(n0 - ns);
-    for (int n = n0; n <= n1; ++n, m += 1.0f) {
-        if (n == ns + SEG) {
-            ns += SEG;
-            m = 0.0f;
-            const double D[3] = {gray->D[0], gray->D[1], gray->D[2]};
-            o = seg_origin(Qd, D, ns);
-            bounds();
+    for (;;) {
+        // samples up to the end of this segment; m counts in float (exact)
+        const int nend = min(n1, ns + SEG - 1);
+        const float mend = (float)(nend - ns);
+        for (; m <= mend; m += 1.0f) {
+            const float lx = __builtin_fmaf(m, Df[0], o.f[0]);
+            const float ly = __builtin_fmaf(m, Df[1], o.f[1]);
+            const float lz = __builtin_fmaf(m, Df[2], o.f[2]);
+            const bool in = (__builtin_floorf(lx) == L[0]) & (__builtin_floorf(ly) == L[1]) &
+                            (__builtin_floorf(lz) == L[2]);
+            if (!in) continue;
+            add_corners<float>(acc, rv, lx - L[0], ly - L[1], lz - L[2]);
         }
-        const float lx = __builtin_fmaf(m, Df[0], o.f[0]);
-        const float ly = __builtin_fmaf(m, Df[1], o.f[1]);
-        const float lz = __builtin_fmaf(m, Df[2], o.f[2]);
-        const bool in = (__builtin_floorf(lx) == L[0]) & (__builtin_floorf(ly) == L[1]) &
-                        (__builtin_floorf(lz) == L[2]);
-        if (!in) continue;
-        add_corners<float>(acc, rv, lx - L[0], ly - L[1], lz - L[2]);
+        if (nend >= n1) return;
+        // rare: the cell's samples of this ray run into the next segment
+        ns += SEG;
+        m = 0.0f;
+        const double D[3] = {gray->D[0], gray->D[1], gray->D[2]};
+        o = seg_origin(Qd, D, ns);
+        bounds();
     }
 }
 
