@@ -95,6 +95,21 @@ def test_error_strings_without_gpu():
     assert lib.cbct_fbs_footprint(ctypes.byref(g), None) == 0
 
 
+def test_representation_limits_are_rejected_before_the_device():
+    """The transpose keeps cell indices and segment numbers in 16 bits:
+    grids above 32000 voxels per axis, or a step so small that sample
+    indices pass 8e6, are refused at plan creation (no GPU needed)."""
+    _native = _built()
+    lib = _native.lib()
+    h = ctypes.c_void_p()
+    g = _native.cbct_geom(32001, 1, 1, 0.001, 1, 1, 16, 16, 1, 1, 100, 200, 1, None, 0)
+    assert lib.cbct_plan_create(ctypes.byref(g), ctypes.byref(h)) == _native.CBCT_EINVAL
+    assert b"32000" in lib.cbct_last_error()
+    g = _native.cbct_geom(8, 8, 8, 1, 1, 1, 16, 16, 1, 1, 100, 200, 1, None, 1e-5)
+    assert lib.cbct_plan_create(ctypes.byref(g), ctypes.byref(h)) == _native.CBCT_EINVAL
+    assert b"step too small" in lib.cbct_last_error()
+
+
 def test_footprint_is_host_arithmetic():
     import paper_1002_3675_amd as cb
     from workloads import head_geometry
