@@ -340,6 +340,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                                                const T *__restrict__ r, T *__restrict__ cells,
                                                T step) {
     __shared__ StagedRay table[TABLE];
+    __shared__ float2 corner[(CB_X + 1) * (CB_Y + 1)];
     const int tid = threadIdx.x;
     // bricks x-fastest, then y, then z; each XCD takes one contiguous range,
     // so the bricks resident on an XCD at a time are neighbours whose
@@ -356,10 +357,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     const float blo[3] = {(float)bb.c0[0], (float)bb.c0[1], (float)bb.c0[2]};
     const float bhi[3] = {(float)min(bb.c0[0] + CB_X, gc.nx), (float)min(bb.c0[1] + CB_Y, gc.ny),
                           (float)min(bb.c0[2] + CB_Z, gc.nz)};
-    // this lane's cell box (same expressions as the brick box, so shared
-    // faces round identically)
-    const float xa = gc.x0 + (float)cx * gc.hx, xb = gc.x0 + (float)(cx + 1) * gc.hx;
-    const float ya = gc.y0 + (float)cy * gc.hy, yb = gc.y0 + (float)(cy + 1) * gc.hy;
+    // this lane's cell faces in z (same expressions as the brick box)
     const float za = gc.z0 + (float)cz * gc.hz, zb = gc.z0 + (float)(cz + 1) * gc.hz;
     const float cxf = (float)cx, cyf = (float)cy, czf = (float)cz;
     T acc[8];
@@ -379,8 +377,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
         // float data stages the footprint in LDS; double reads the ray
         // table and the residual at full precision from memory
         const bool staged = sizeof(T) == 4 && bw * bh <= TABLE;
+        __syncthreads();  // readers of the previous view are done
+        // the brick's (CB_X + 1) x (CB_Y + 1) cell corners in the xy plane,
+        // projected: u / sdd and 1 / depth (the corner expressions of
+        // box_footprint, shared by the 8 x 8 cells of every layer)
+        if (tid < (CB_X + 1) * (CB_Y + 1)) {
+            const int a = tid % (CB_X + 1), b = tid / (CB_X + 1);
+            const float x = gc.x0 + (float)(bb.c0[0] + a) * gc.hx;
+            const float y = gc.y0 + (float)(bb.c0[1] + b) * gc.hy;
+            const float wx = x - vc.src[0], wy = y - vc.src[1];
+            const float n = wx * vc.cs + wy * vc.sn, d = wy * vc.cs - wx * vc.sn;
+            const float ri = rcp(d);
+            corner[tid] = make_float2(n * ri, ri);
+        }
         if (staged) {
-            __syncthreads();  // readers of the previous view are done
             // element t -> (row, col) by a float reciprocal: exact for
             // t < 2^13, since (t + 1/2)/bw stays >= 1/(2 bw) from an integer
             const float ibw = 1.0f / (float)bw;
@@ -414,11 +424,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
                 e.r = (float)rk[pix];
                 table[t] = e;
             }
-            __syncthreads();
         }
+        __syncthreads();
         if (!valid) continue;
-        float umin, umax, vmin, vmax;
-        box_footprint(vc, dc.sdd, xa, xb, ya, yb, za, zb, umin, umax, vmin, vmax);
+        // the cell's detector rectangle from its four xy corners (u) and
+        // the extreme depths at its z faces (v), as box_footprint does
+        const int cc = (cy - bb.c0[1]) * (CB_X + 1) + (cx - bb.c0[0]);
+        const float2 k00 = corner[cc], k10 = corner[cc + 1];
+        const float2 k01 = corner[cc + CB_X + 1], k11 = corner[cc + CB_X + 2];
+        const float umin = dc.sdd * fminf(fminf(k00.x, k10.x), fminf(k01.x, k11.x));
+        const float umax = dc.sdd * fmaxf(fmaxf(k00.x, k10.x), fmaxf(k01.x, k11.x));
+        const float ia = fmaxf(fmaxf(k00.y, k10.y), fmaxf(k01.y, k11.y));  // 1 / nearest
+        const float ib = fminf(fminf(k00.y, k10.y), fminf(k01.y, k11.y));  // 1 / farthest
+        const float v0 = za * ia, v1 = za * ib, v2 = zb * ia, v3 = zb * ib;
+        const float vmin = dc.sdd * fminf(fminf(v0, v1), fminf(v2, v3));
+        const float vmax = dc.sdd * fmaxf(fmaxf(v0, v1), fmaxf(v2, v3));
         int i0, i1, j0, j1;
         pixel_range(dc, nu, nv, umin, umax, vmin, vmax, i0, i1, j0, j1);
         // the cell lies in the brick: keep its pixels inside the brick's
