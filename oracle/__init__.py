@@ -76,8 +76,9 @@ def _load():
             lib.or_default_inner.restype = ctypes.c_int
             lib.or_fbs_solve.argtypes = [_I, _D, _D, _D, _D, ctypes.c_double, ctypes.c_int,
                                          _I, _D, ctypes.c_double, _I, ctypes.c_double,
-                                         ctypes.c_int, _D, _D, _D]
+                                         ctypes.c_int, ctypes.c_int, _D, _D, _D]
             lib.or_fbs_solve.restype = ctypes.c_int
+            lib.or_eq2_backproject.argtypes = [_I, _D, _D, _D, _D]
             lib.or_threads.argtypes = []
             lib.or_threads.restype = ctypes.c_int
             _lib = lib
@@ -133,6 +134,18 @@ def backproject(g, y):
     y = _f64(y).reshape(_pshape(g))
     f = np.empty(_vshape(g))
     lib.or_backproject(dims.ctypes.data_as(_I), _dp(par), _dp(ang), _dp(y), _dp(f))
+    return f
+
+
+def eq2_backproject(g, y):
+    """Eq. (2) of the paper as an operator on residuals y, on the scale of
+    the matrix transpose: sum over views of L^3/(L0 l^2) times the bilinear
+    interpolant of y at the voxel's imager point, times hx hy hz/(au av)."""
+    lib = _load()
+    dims, par, ang = _pack(g)
+    y = _f64(y).reshape(_pshape(g))
+    f = np.empty(_vshape(g))
+    lib.or_eq2_backproject(dims.ctypes.data_as(_I), _dp(par), _dp(ang), _dp(y), _dp(f))
     return f
 
 
@@ -271,7 +284,7 @@ def coarse_geometry(g):
 
 
 def fbs_solve(g, Y, mu, iters, f0=None, beta=None, eps=1e-3, n_inner=None,
-              tv_weight=1.0, clip_mode=0, trace=False):
+              tv_weight=1.0, clip_mode=0, trace=False, gradient="matched"):
     """Algorithm A1 with the coarse-to-fine schedule.
 
     iters: outer iterations per level, coarse first (length 1 or 2).
@@ -288,9 +301,10 @@ def fbs_solve(g, Y, mu, iters, f0=None, beta=None, eps=1e-3, n_inner=None,
     used = np.zeros(4)
     tr = np.zeros((int(sum(iters)) + nl, 4)) if trace else None
     rep = np.zeros(4)
+    gm = {"matched": 0, "eq2": 1}[gradient]
     rc = lib.or_fbs_solve(dims.ctypes.data_as(_I), _dp(par), _dp(ang), _dp(Y), _dp(f), mu, nl,
                           it.ctypes.data_as(_I), _dp(b), eps, k.ctypes.data_as(_I), tv_weight,
-                          clip_mode, _dp(used), _dp(tr), _dp(rep))
+                          clip_mode, gm, _dp(used), _dp(tr), _dp(rep))
     if rc != 0:
         raise ValueError("oracle fbs_solve: invalid arguments")
     return dict(f=f, used_beta=used[:nl].copy(), used_inner=used[2:2 + nl].astype(int),

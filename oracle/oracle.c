@@ -146,6 +146,60 @@ static void stencil(const geom_t *g, const double p[3], long idx0[3], double w[3
     }
 }
 
+/* ------------------------------------------------------- Eq. (2) ---- */
+
+/* The paper's gather-form gradient, Eq. (2), as an operator on residuals
+ * y ([n_views][nv][nu]) with the scale of the matrix transpose:
+ *   out(x_v) = (hx hy hz / (au av)) * sum_theta L^3 / (L0 l^2) * y~(u*, v*)
+ * where, for view theta, (u*, v*) is the imager point on the ray from the
+ * source through the voxel centre x_v, l = |x_v - s| the source-voxel
+ * distance, L = sqrt(L0^2 + u*^2 + v*^2) the source-imager-point distance
+ * and L0 = SDD.  (hx hy hz / (au av)) * (P^theta)^* approximates the
+ * discrete transpose (the sum over pixels is (1/(au av)) times the
+ * imager integral, the sum over voxels (1/(hx hy hz)) times the volume
+ * integral), so Step 1 keeps the form g = f - tau * out.
+ * y~ is the bilinear interpolant of the pixel-centre values, zero beyond
+ * the outermost pixel centres (the paper leaves the interpolation open). */
+void or_eq2_backproject(const int *dims, const double *par, const double *angles,
+                        const double *y, double *out)
+{
+    geom_t g = unpack(dims, par, angles);
+    double scale = g.hx * g.hy * g.hz / (g.au * g.av);
+    long nvox = (long)g.nx * g.ny * g.nz;
+#pragma omp parallel for schedule(static)
+    for (long v = 0; v < nvox; ++v) {
+        long i = v % g.nx, j = (v / g.nx) % g.ny, k = v / ((long)g.nx * g.ny);
+        double x = ((double)i - 0.5 * (g.nx - 1)) * g.hx;
+        double yy = ((double)j - 0.5 * (g.ny - 1)) * g.hy;
+        double z = ((double)k - 0.5 * (g.nz - 1)) * g.hz;
+        double sum = 0.0;
+        for (int t = 0; t < g.nviews; ++t) {
+            double th = view_angle(&g, t), c = cos(th), sn = sin(th);
+            /* source (sad sin, -sad cos, 0); imager axes e_u = (cos, sin, 0),
+             * e_v = z; the central ray runs along e_w = (-sin, cos, 0) */
+            double wx = x - g.sad * sn, wy = yy + g.sad * c, wz = z;
+            double depth = -wx * sn + wy * c;
+            double us = g.sdd * (wx * c + wy * sn) / depth;
+            double vs = g.sdd * wz / depth;
+            double l2 = wx * wx + wy * wy + wz * wz;
+            double L = sqrt(g.sdd * g.sdd + us * us + vs * vs);
+            double w = L * L * L / (g.sdd * l2);
+            double fi = us / g.au + 0.5 * (g.nu - 1), fj = vs / g.av + 0.5 * (g.nv - 1);
+            double i0 = floor(fi), j0 = floor(fj), a = fi - i0, b = fj - j0;
+            const double *yt = y + (long)t * g.nu * g.nv;
+            double val = 0.0;
+            for (int dj = 0; dj < 2; ++dj)
+                for (int di = 0; di < 2; ++di) {
+                    long ii = (long)i0 + di, jj = (long)j0 + dj;
+                    if (ii < 0 || ii >= g.nu || jj < 0 || jj >= g.nv) continue;
+                    val += (di ? a : 1.0 - a) * (dj ? b : 1.0 - b) * yt[jj * g.nu + ii];
+                }
+            sum += w * val;
+        }
+        out[v] = scale * sum;
+    }
+}
+
 /* ---------------------------------------------------------------- P ---- */
 
 /* y = P f: the discrete cone-beam projection P^theta of Eq. (1), for every
@@ -532,7 +586,7 @@ static void energies(const int *dims, const double *par, const double *angles,
 static void fbs_level(const int *dims, const double *par, const double *angles,
                       const double *Y, double *f, double mu, double beta, double eps,
                       int n_inner, int iters, double tv_weight, int clip_mode,
-                      double *trace)
+                      int grad_mode, double *trace)
 {
     geom_t g = unpack(dims, par, angles);
     long nvox = (long)g.nx * g.ny * g.nz, nmeas = (long)g.nviews * g.nu * g.nv;
@@ -545,7 +599,10 @@ static void fbs_level(const int *dims, const double *par, const double *angles,
         if (trace) energies(dims, par, angles, f, Y, mu, eps, trace + 4 * it);
         /* Step 1 (update): g = f - (mu V / beta) dE2/df */
         or_data_energy(dims, par, angles, f, Y, r);
-        or_backproject(dims, par, angles, r, grad);
+        if (grad_mode == 1)
+            or_eq2_backproject(dims, par, angles, r, grad);  /* Eq. (2) as printed */
+        else
+            or_backproject(dims, par, angles, r, grad);      /* matched transpose */
         for (long v = 0; v < nvox; ++v) gaux[v] = f[v] - tau * grad[v];
         /* Steps 2 and 3 (minimise, correct), started from the current f */
         or_tv_prox(dims, h, gaux, f, beta, eps, n_inner, 0.0, clip_mode, tv_weight, NULL);
@@ -562,11 +619,12 @@ static void fbs_level(const int *dims, const double *par, const double *angles,
  *   used[0..3] (optional) receive beta and n_inner per level.
  *   trace (optional): rows of (E, E_eps, E1, E2), iters[l]+1 rows per level.
  *   report (optional): E, E_eps, E1, E2 of the returned f (fine level).
+ *   grad_mode 0: Step 1 with the matched transpose; 1: with Eq. (2).
  * Returns 0, or -1 on invalid sizes. */
 int or_fbs_solve(const int *dims, const double *par, const double *angles,
                  const double *Y, double *f, double mu, int n_levels,
                  const int *iters, const double *beta, double eps,
-                 const int *n_inner, double tv_weight, int clip_mode,
+                 const int *n_inner, double tv_weight, int clip_mode, int grad_mode,
                  double *used, double *trace, double *report)
 {
     geom_t g = unpack(dims, par, angles);
@@ -608,7 +666,7 @@ int or_fbs_solve(const int *dims, const double *par, const double *angles,
         if (k <= 0) k = or_default_inner(h, b, eps);
         if (used) { used[l] = b; used[2 + l] = (double)k; }
         fbs_level(d, p, angles, lY[l], lf[l], mu, b, eps, k, iters[l], tv_weight,
-                  clip_mode, tr);
+                  clip_mode, grad_mode, tr);
         if (tr) tr += 4 * (iters[l] + 1);
         if (l == 0 && n_levels == 2) or_prolong(ldims[0], dims, fcoarse, f);
     }
