@@ -108,6 +108,18 @@ int cbct_backproject(const cbct_plan *p, const float *y, float *f, void *stream)
 int cbct_backproject_update(const cbct_plan *p, const float *r, const float *f,
                             double tau, float *g, void *stream);
 
+/* The paper's gather-form gradient, Eq. (2), as an operator on residuals
+ * y ([n_views][nv][nu], u fastest), on the scale of the matrix transpose:
+ *   f(x_v) = hx hy hz / (au av) * sum_theta L^3 / (L0 l^2) * y~(u*, v*),
+ * with (u*, v*) the imager point of the ray from the source through the
+ * voxel centre x_v, l the source-voxel distance, L the source-imager-point
+ * distance, L0 = sdd, and y~ the bilinear interpolant of the pixel-centre
+ * values, zero beyond the outermost centres.  One lane per voxel, the
+ * views summed in order: no atomics, deterministic.  It approximates
+ * cbct_backproject (first order in the pixel pitch) and is not its exact
+ * transpose.  f is written over; device pointers; EINVAL on NULL. */
+int cbct_backproject_eq2(const cbct_plan *p, const float *y, float *f, void *stream);
+
 /* Float64 versions of cbct_project / cbct_backproject (same algorithm in
  * double precision; for derivative checks). */
 int cbct_project_f64(const cbct_plan *p, const double *f, double *y, void *stream);
@@ -145,7 +157,10 @@ int cbct_plan_lambda(const cbct_plan *p, int32_t n_iter, double *lambda_host,
  * with lambda from 30 power-iteration steps on that level.  n_inner[level]
  * <= 0 selects min(200, ceil(3 (1 + 4 sum_a h_a^-2 / (eps beta)))).
  * eps is the TV smoothing (1/mm^2).  trace_energy = 1 computes E at the
- * start of every outer iteration and at the end (one host sync each). */
+ * start of every outer iteration and at the end (one host sync each).
+ * gradient selects Step 1's gradient of E2: 0 the exact transpose of the
+ * projector (cbct_backproject; then E_eps never increases), 1 the paper's
+ * Eq. (2) as printed (cbct_backproject_eq2, far cheaper, not matched). */
 typedef struct cbct_fbs_params {
     double mu;
     int32_t n_levels;
@@ -154,6 +169,7 @@ typedef struct cbct_fbs_params {
     double eps;
     int32_t n_inner[2];
     int32_t trace_energy;
+    int32_t gradient;
 } cbct_fbs_params;
 
 /* Filled by the solver.  E, E_eps, E1, E2 describe the returned volume
@@ -208,7 +224,8 @@ size_t cbct_fbs_footprint(const cbct_geom *g, const cbct_fbs_params *prm);
 #define CBCT_KERNEL_TV_SWEEP 4   /* one projected TV gradient step */
 #define CBCT_KERNEL_TV_ENERGY 5  /* E1 partial sums */
 #define CBCT_KERNEL_OTHER 6      /* reductions, fills, transfers */
-#define CBCT_KERNEL_COUNT 7
+#define CBCT_KERNEL_EQ2 7        /* Eq. (2) gradient (+ Step 1) */
+#define CBCT_KERNEL_COUNT 8
 int cbct_kernel_timing(int32_t enable);
 int cbct_kernel_timing_read(int32_t kernel, int64_t *launches, double *total_ms);
 

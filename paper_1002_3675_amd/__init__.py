@@ -190,6 +190,18 @@ class Plan:
             check(fn(self._h, _ptr(y), _ptr(f), _stream_of(y)), "cbct_backproject")
         return f
 
+    def backproject_eq2(self, y, out=None):
+        """The paper's Eq. (2) applied to residuals y, on the transpose's
+        scale (float32): the cheap, unmatched approximation of P^T y."""
+        torch = _torch()
+        _check_tensor(y, self.geom.proj_shape, torch.float32, "y")
+        f = self._new(self.geom.vol_shape, torch.float32) if out is None else out
+        _check_tensor(f, self.geom.vol_shape, torch.float32, "out")
+        with torch.cuda.device(self.device):
+            check(self._lib.cbct_backproject_eq2(self._h, _ptr(y), _ptr(f), _stream_of(y)),
+                  "cbct_backproject_eq2")
+        return f
+
     def backproject_update(self, r, f, tau, out=None):
         """g = f - tau * P^T r (Step 1 of Algorithm A1)."""
         torch = _torch()
@@ -254,6 +266,7 @@ class FbsParams:
     eps: float = 1e-3
     n_inner: Optional[Sequence[int]] = None  # None / <= 0 -> default rule
     trace_energy: bool = False
+    gradient: str = "matched"             # "matched" (P^T) or "eq2" (the paper's Eq. (2))
 
     def to_c(self):
         n = len(self.iters)
@@ -268,6 +281,9 @@ class FbsParams:
             p.n_inner[l] = int(self.n_inner[l]) if self.n_inner is not None else 0
         p.eps = float(self.eps)
         p.trace_energy = int(bool(self.trace_energy))
+        if self.gradient not in ("matched", "eq2"):
+            raise ValueError("gradient must be 'matched' or 'eq2'")
+        p.gradient = 1 if self.gradient == "eq2" else 0
         return p
 
 

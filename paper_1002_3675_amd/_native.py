@@ -15,7 +15,7 @@ CBCT_ENOMEM = -2
 CBCT_EHIP = -3
 CBCT_ENONFINITE = -4
 
-KERNELS = ("pad", "project", "cells", "gather", "tv_sweep", "tv_energy", "other")
+KERNELS = ("pad", "project", "cells", "gather", "tv_sweep", "tv_energy", "other", "eq2")
 
 
 class cbct_geom(ctypes.Structure):
@@ -32,7 +32,7 @@ class cbct_fbs_params(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_double), ("n_levels", ctypes.c_int32),
                 ("iters", ctypes.c_int32 * 2), ("beta", ctypes.c_double * 2),
                 ("eps", ctypes.c_double), ("n_inner", ctypes.c_int32 * 2),
-                ("trace_energy", ctypes.c_int32)]
+                ("trace_energy", ctypes.c_int32), ("gradient", ctypes.c_int32)]
 
 
 class cbct_fbs_report(ctypes.Structure):
@@ -75,6 +75,7 @@ SIGNATURES = {
     "cbct_kernel_timing_read": (ctypes.c_int, [_I32, ctypes.POINTER(ctypes.c_int64),
                                                ctypes.POINTER(_D)]),
     "cbct_probe_fma_rate": (ctypes.c_int, [_I32, ctypes.POINTER(_D), _P]),
+    "cbct_backproject_eq2": (ctypes.c_int, [_P, _P, _P, _P]),
     "cbct_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "cbct_last_error": (ctypes.c_char_p, []),
 }

@@ -304,6 +304,8 @@ extern "C" int cbct_plan_create(const cbct_geom *gin, cbct_plan **out) {
             v.Vz = (float)v.Vzd;
             v.cs = (float)cs;
             v.sn = (float)sn;
+            v.csd = cs;
+            v.snd = sn;
         }
         DetConst &d = p->det;
         d.u0d = -0.5 * (g.nu - 1) * g.au;
@@ -311,6 +313,7 @@ extern "C" int cbct_plan_create(const cbct_geom *gin, cbct_plan **out) {
         d.aud = g.au;
         d.avd = g.av;
         d.sdd2d = g.sdd * g.sdd;
+        d.sddd = g.sdd;
         d.u0 = (float)d.u0d;
         d.v0 = (float)d.v0d;
         d.au = (float)g.au;
@@ -432,6 +435,14 @@ extern "C" int cbct_backproject_update(const cbct_plan *p, const float *r, const
     if (!f) return set_error(CBCT_EINVAL, "f is NULL");
     if (!isfinite(tau)) return set_error(CBCT_EINVAL, "tau not finite");
     return backproject_impl<float>(p, r, f, tau, g, as_stream(stream));
+}
+
+extern "C" int cbct_backproject_eq2(const cbct_plan *p, const float *y, float *f,
+                                    void *stream) {
+    if (!p || !y || !f) return set_error(CBCT_EINVAL, "NULL argument");
+    hipStream_t s = as_stream(stream);
+    return check_hip(timed(CBCT_KERNEL_EQ2, s, [&] { return launch_eq2(*p, y, nullptr, 0.0, f, s); }),
+                     "eq2 kernel");
 }
 
 extern "C" int cbct_project_f64(const cbct_plan *p, const double *f, double *y, void *stream) {
@@ -659,13 +670,17 @@ int validate_params(const cbct_geom &g, const cbct_fbs_params *prm) {
     }
     if (prm->n_levels == 2 && ((g.nx | g.ny | g.nz | g.nu | g.nv) & 1))
         return set_error(CBCT_EINVAL, "two levels need even nx, ny, nz, nu, nv");
+    if (prm->gradient != 0 && prm->gradient != 1)
+        return set_error(CBCT_EINVAL, "gradient must be 0 (transpose) or 1 (Eq. (2))");
     return CBCT_OK;
 }
 
-size_t level_bytes(const cbct_geom &g, bool own_yf) {
+// Device bytes of one level's state; the Eq. (2) gradient needs no
+// transpose workspace.
+size_t level_bytes(const cbct_geom &g, bool own_yf, int gradient) {
     const size_t nvox = nvox_of(g), nmeas = nmeas_of(g);
-    size_t b = sizeof(float) * (2 * nvox + nmeas + padded_of(g)) +
-               bp_workspace_bytes(g, sizeof(float));
+    size_t b = sizeof(float) * (2 * nvox + nmeas + padded_of(g));
+    if (gradient == 0) b += bp_workspace_bytes(g, sizeof(float));
     if (own_yf) b += sizeof(float) * (nvox + nmeas);
     return b;
 }
@@ -720,8 +735,13 @@ int fbs_iteration(cbct_fbs_state *st, Level &L, hipStream_t s, bool have_residua
     const cbct_plan &p = *L.plan;
     // Step 1 (update): r = P f - Y, g = f - tau P^T r
     int rc = have_residual ? CBCT_OK : level_residual(st, L, s, false, nullptr);
-    if (!rc) rc = check_hip(timed(CBCT_KERNEL_CELLS, s, [&] { return launch_backproject_cells<float>(p, L.r, L.cells, s); }), "cells");
-    if (!rc) rc = check_hip(timed(CBCT_KERNEL_GATHER, s, [&] { return launch_gather_cells<float>(p, L.cells, L.f, L.tau, L.g, s); }), "gather");
+    if (st->prm.gradient == 1) {
+        // the paper's Eq. (2) as printed, fused with the update
+        if (!rc) rc = check_hip(timed(CBCT_KERNEL_EQ2, s, [&] { return launch_eq2(p, L.r, L.f, L.tau, L.g, s); }), "eq2");
+    } else {
+        if (!rc) rc = check_hip(timed(CBCT_KERNEL_CELLS, s, [&] { return launch_backproject_cells<float>(p, L.r, L.cells, s); }), "cells");
+        if (!rc) rc = check_hip(timed(CBCT_KERNEL_GATHER, s, [&] { return launch_gather_cells<float>(p, L.cells, L.f, L.tau, L.g, s); }), "gather");
+    }
     // Steps 2 and 3 (minimise, correct), from z0 = f
     if (!rc)
         rc = prox_sweeps(p.grid, L.nvox, L.g, L.f, L.z, L.beta, st->prm.eps, L.n_inner,
@@ -734,8 +754,8 @@ int fbs_iteration(cbct_fbs_state *st, Level &L, hipStream_t s, bool have_residua
 extern "C" size_t cbct_fbs_footprint(const cbct_geom *g, const cbct_fbs_params *prm) {
     if (validate_geom(g) || validate_params(*g, prm)) return 0;
     size_t b = sizeof(float) * (nvox_of(*g) + nmeas_of(*g));  // caller's f and Y
-    b += level_bytes(*g, false);
-    if (prm->n_levels == 2) b += level_bytes(coarse_geom(*g), true);
+    b += level_bytes(*g, false, prm->gradient);
+    if (prm->n_levels == 2) b += level_bytes(coarse_geom(*g), true, prm->gradient);
     // partials and scalars
     dim3 pg((g->nu + 31) / 32, (g->nv + 7) / 8, g->n_views);  // projector tile grid
     size_t np = std::max((size_t)pg.x * pg.y * pg.z,
@@ -796,8 +816,10 @@ extern "C" int cbct_fbs_init(const cbct_plan *fine, const float *Y, float *f,
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.z, sizeof(float) * L.nvox, s);
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.r, sizeof(float) * L.nmeas, s);
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.pad, sizeof(float) * padded_count(p), s);
-            if (!rc) rc = alloc_owned(st.get(), (void **)&L.cells, bp_workspace_bytes(p.g, sizeof(float)), s);
-            if (!rc) rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_bp_prepare(p, L.cells, sizeof(float), s); }), "ray table");
+            if (!rc && prm->gradient == 0) {
+                rc = alloc_owned(st.get(), (void **)&L.cells, bp_workspace_bytes(p.g, sizeof(float)), s);
+                if (!rc) rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_bp_prepare(p, L.cells, sizeof(float), s); }), "ray table");
+            }
         }
         if (!rc && st->n_levels == 2) {
             const cbct_geom &g = fine->g;

@@ -512,6 +512,62 @@ __global__ __launch_bounds__(256) void k_gather(GridConst gc, const T *__restric
     out[v] = f ? f[v] - tau * s : s;
 }
 
+// The paper's Eq. (2) gradient, voxel-driven: one lane per voxel sums over
+// the views L^3/(L0 l^2) times the bilinear interpolant of the residual at
+// the voxel's imager point (zero beyond the outermost pixel centres), and
+// scales by hx hy hz / (au av) (the transpose's scale).  Geometry in
+// double, the interpolation in float, the sum in double.  L^3/(L0 l^2)
+// is evaluated as L0^2 l / d^3 (L/l = L0/d along the ray, d the depth of
+// the voxel along the central ray).
+constexpr int Q_BX = 64, Q_BY = 4;
+
+__global__ __launch_bounds__(256) void k_eq2(const ViewConst *__restrict__ views, DetConst dc,
+                                             GridConst gc, double hx, double hy, double hz,
+                                             int nu, int nv, int nviews,
+                                             const float *__restrict__ r,
+                                             const float *__restrict__ f, double scale,
+                                             double tau, float *__restrict__ out) {
+    const int i = blockIdx.x * Q_BX + threadIdx.x;
+    const int j = blockIdx.y * Q_BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= gc.nx || j >= gc.ny) return;
+    const double sdd = dc.sddd, sdd2 = dc.sdd2d;
+    const double iau = 1.0 / dc.aud, iav = 1.0 / dc.avd;
+    const double ci = -dc.u0d * iau, cj = -dc.v0d * iav;  // index of u = 0, v = 0
+    double sum = 0.0;
+    for (int t = 0; t < nviews; ++t) {
+        const ViewConst vc = views[t];
+        // source-to-voxel vector in mm (index coordinates of the voxel
+        // centre minus those of the source, times the spacing)
+        const double wx = ((double)i - vc.Qd[0]) * hx;
+        const double wy = ((double)j - vc.Qd[1]) * hy;
+        const double wz = ((double)k - vc.Qd[2]) * hz;
+        const double n = wx * vc.csd + wy * vc.snd;      // along e_u
+        const double d = wy * vc.csd - wx * vc.snd;      // along e_w (depth)
+        const double id = 1.0 / d;
+        const double fi = sdd * n * id * iau + ci;       // fractional pixel indices
+        const double fj = sdd * wz * id * iav + cj;
+        const double l = __builtin_sqrt(wx * wx + wy * wy + wz * wz);
+        const double w = sdd2 * l * (id * id * id);
+        const double i0d = __builtin_floor(fi), j0d = __builtin_floor(fj);
+        const float a = (float)(fi - i0d), b = (float)(fj - j0d);
+        const int i0 = (int)fmax(fmin(i0d, (double)nu), -2.0);
+        const int j0 = (int)fmax(fmin(j0d, (double)nv), -2.0);
+        const float *rt = r + (long long)t * nu * nv;
+        const bool in0 = i0 >= 0 && i0 < nu, in1 = i0 + 1 >= 0 && i0 + 1 < nu;
+        const bool jn0 = j0 >= 0 && j0 < nv, jn1 = j0 + 1 >= 0 && j0 + 1 < nv;
+        const float r00 = (in0 && jn0) ? rt[(long long)j0 * nu + i0] : 0.0f;
+        const float r10 = (in1 && jn0) ? rt[(long long)j0 * nu + i0 + 1] : 0.0f;
+        const float r01 = (in0 && jn1) ? rt[(long long)(j0 + 1) * nu + i0] : 0.0f;
+        const float r11 = (in1 && jn1) ? rt[(long long)(j0 + 1) * nu + i0 + 1] : 0.0f;
+        const float v0 = r00 + a * (r10 - r00), v1 = r01 + a * (r11 - r01);
+        sum += w * (double)(v0 + b * (v1 - v0));
+    }
+    const long long v = (long long)i + (long long)gc.nx * (j + (long long)gc.ny * k);
+    const double s = scale * sum;
+    out[v] = f ? (float)((double)f[v] - tau * s) : (float)s;
+}
+
 }  // namespace
 
 namespace {
@@ -572,6 +628,15 @@ hipError_t launch_gather_cells(const cbct_plan &p, const void *ws, const T *f, d
     dim3 grid((p.g.nx + G_BX - 1) / G_BX, (p.g.ny + G_BY - 1) / G_BY, p.g.nz);
     hipLaunchKernelGGL(k_gather<T>, grid, dim3(G_BX, G_BY), 0, s, p.grid, (const T *)ws, f,
                        (T)tau, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_eq2(const cbct_plan &p, const float *r, const float *f, double tau,
+                      float *out, hipStream_t s) {
+    const double scale = p.g.hx * p.g.hy * p.g.hz / (p.g.au * p.g.av);
+    dim3 grid((p.g.nx + Q_BX - 1) / Q_BX, (p.g.ny + Q_BY - 1) / Q_BY, p.g.nz);
+    hipLaunchKernelGGL(k_eq2, grid, dim3(Q_BX, Q_BY), 0, s, p.d_views, p.det, p.grid, p.g.hx,
+                       p.g.hy, p.g.hz, p.g.nu, p.g.nv, p.g.n_views, r, f, scale, tau, out);
     return hipGetLastError();
 }
 

@@ -30,7 +30,7 @@ struct ViewConst {
     float cs, sn;  // cos(theta), sin(theta)
     double Qd[3];  // the same constants in double for the FP64 kernels
     double Wd[2], Ud[2], Vzd;
-    double pad_;
+    double csd, snd;  // cos(theta), sin(theta) in double
 };
 
 // The dispatcher hands the workgroups of a launch to the 8 XCDs of the chip
@@ -50,7 +50,7 @@ struct DetConst {
     float u0, au, v0, av;  // pixel centre u = u0 + i*au, v = v0 + j*av (mm)
     float sdd2;            // sdd^2
     float sdd;
-    double u0d, aud, v0d, avd, sdd2d;
+    double u0d, aud, v0d, avd, sdd2d, sddd;
 };
 
 struct GridConst {
@@ -106,6 +106,10 @@ hipError_t launch_backproject_cells(const cbct_plan &p, const T *r, void *ws, hi
 template <typename T>
 hipError_t launch_gather_cells(const cbct_plan &p, const void *ws, const T *f, double tau,
                                T *out, hipStream_t s);
+// Eq. (2) gradient of the residual r: out = B r, or out = f - tau * B r
+// when f is given
+hipError_t launch_eq2(const cbct_plan &p, const float *r, const float *f, double tau,
+                      float *out, hipStream_t s);
 hipError_t launch_count_samples(const cbct_plan &p, unsigned long long *count, hipStream_t s);
 
 size_t project_partials_count(const cbct_plan &p);
