@@ -71,6 +71,28 @@ def measured_traffic(kernel, mix):
     return None
 
 
+def eq2_comparison(torch, cb, plan, Y, params, f_matched, rep_matched, yr, fb, ms_pt, reps):
+    """The paper's Eq. (2) gradient in place of the matched transpose: the
+    operator's time at the fine level, and the same head solve with it."""
+    import dataclasses
+    g = plan.geom
+    ms_op = time_op(torch, lambda: plan.backproject_eq2(yr, out=fb), reps)
+    p2 = dataclasses.replace(params, gradient="eq2")
+    cb.fbs_solve(plan, Y, p2)  # warm (beta is cached in the plan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f2, rep2 = cb.fbs_solve(plan, Y, p2)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    diff = float(torch.linalg.vector_norm((f2 - f_matched).double()) /
+                 torch.linalg.vector_norm(f_matched.double()))
+    vv = g.nx * g.ny * g.nz * g.n_views
+    return {"op_fine_ms": ms_op, "gvoxel_views_per_s": vv / (ms_op * 1e-3) / 1e9,
+            "speedup_vs_matched_PT": ms_pt / ms_op, "solve_s": dt,
+            "final_energy": rep2.E, "final_energy_matched": rep_matched.E,
+            "rel_l2_vs_matched_solution": diff}
+
+
 def operator_rooflines(g, samples, ms_p, ms_pt):
     """P and P^T at the fine level against both ceilings: algorithmic HBM
     bytes (P: read the volume, write the projections; P^T: read the
@@ -273,8 +295,9 @@ def serving_benchmark(torch, cb, n_req, seed=5000, load=0.8):
 def lowdose_sweep(torch, cb):
     """Head geometry, 20 and 30 views, I0 in {1e4, 2.5e4} with Gaussian
     electronic noise (sigma 5 counts), mu in {5e-4, 1e-3, 2e-3}, 30 + 30
-    iterations: relative L2 error to the voxelised phantom over the grid and
-    over the field of view seen by every view."""
+    iterations (plus mu = 1e-3 with the paper's Eq. (2) gradient): relative
+    L2 error to the voxelised phantom over the grid and over the field of
+    view seen by every view."""
     import numpy as np
     from workloads import fov_mask, lowdose_case, voxelise
     rows = []
@@ -287,8 +310,10 @@ def lowdose_sweep(torch, cb):
                 mask = fov_mask(case.geom)
             plan = cb.Plan(case.geom)
             Y = torch.as_tensor(case.Y, dtype=torch.float32, device="cuda")
-            for mu in (5e-4, 1e-3, 2e-3):
-                p = cb.FbsParams(mu=mu, iters=(30, 30), eps=1e-3, trace_energy=True)
+            runs = [(mu, "matched") for mu in (5e-4, 1e-3, 2e-3)] + [(1e-3, "eq2")]
+            for mu, grad in runs:
+                p = cb.FbsParams(mu=mu, iters=(30, 30), eps=1e-3, trace_energy=True,
+                                 gradient=grad)
                 cb.fbs_solve(plan, Y, p)  # beta setup for this data size
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -298,10 +323,10 @@ def lowdose_sweep(torch, cb):
                 fn = f.cpu().double().numpy()
                 err = np.linalg.norm(fn - truth) / np.linalg.norm(truth)
                 err_fov = np.linalg.norm((fn - truth)[mask]) / np.linalg.norm(truth[mask])
-                rows.append({"views": views, "I0": i0, "mu": mu, "rel_l2": err,
-                             "rel_l2_fov": err_fov, "recon_s": dt, "E": rep.E})
-                log("lowdose views=%d I0=%g mu=%g rel %.4f fov %.4f %.2f s"
-                    % (views, i0, mu, err, err_fov, dt))
+                rows.append({"views": views, "I0": i0, "mu": mu, "gradient": grad,
+                             "rel_l2": err, "rel_l2_fov": err_fov, "recon_s": dt, "E": rep.E})
+                log("lowdose views=%d I0=%g mu=%g %s rel %.4f fov %.4f %.2f s"
+                    % (views, i0, mu, grad, err, err_fov, dt))
     return rows
 
 
@@ -441,6 +466,7 @@ def main():
     fb = torch.empty_like(fr)
     ms_p = time_op(torch, lambda: plan.project(fr, out=yb), args.ops_reps)
     ms_pt = time_op(torch, lambda: plan.backproject(yr, out=fb), args.ops_reps)
+    eq2 = eq2_comparison(torch, cb, plan, Y, params, f, rep, yr, fb, ms_pt, args.ops_reps)
 
     out = {
         "metric": METRIC,
@@ -475,6 +501,7 @@ def main():
         "operators_fine": operator_rooflines(g, s_f, ms_p, ms_pt),
         "alu_measured_tflops": {"fp32_fma": cb.probe_fma_rate(False),
                                 "fp64_fma": cb.probe_fma_rate(True)},
+        "paper_eq2": eq2,
         "per_kernel": per_kernel,
         "roofline": roofline,
         "paper_context": "77-130 s per reconstruction on a Tesla C1060 (different "
