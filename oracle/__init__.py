@@ -149,6 +149,15 @@ def eq2_backproject(g, y):
     return f
 
 
+def log_counts(counts, i0=None, flat=None, min_count=1.0):
+    """Line integrals from detector counts (the log transform before the
+    method): y = ln(I0 / max(I, min_count)), with I0 the open-beam count,
+    per pixel from a flat field or one number for all pixels."""
+    counts = _f64(counts)
+    ref = _f64(flat) if flat is not None else float(i0)
+    return np.log(ref / np.maximum(counts, float(min_count)))
+
+
 def count_samples(g) -> int:
     lib = _load()
     dims, par, ang = _pack(g)
