@@ -120,6 +120,15 @@ int cbct_backproject_update(const cbct_plan *p, const float *r, const float *f,
  * transpose.  f is written over; device pointers; EINVAL on NULL. */
 int cbct_backproject_eq2(const cbct_plan *p, const float *y, float *f, void *stream);
 
+/* Line integrals from detector counts, the step before the method:
+ * y[i] = ln(ref / max(counts[i], min_count)) for i < n, with ref = flat[i]
+ * (an open-beam flat field, same layout as counts) or, when flat is NULL,
+ * ref = i0 for every pixel.  Evaluated in double, rounded to float.  Device
+ * pointers; y may alias counts.  EINVAL for NULL counts or y, n < 0,
+ * min_count <= 0, or (flat NULL and i0 <= 0). */
+int cbct_log_counts(const float *counts, const float *flat, double i0, double min_count,
+                    float *y, int64_t n, void *stream);
+
 /* Float64 versions of cbct_project / cbct_backproject (same algorithm in
  * double precision; for derivative checks). */
 int cbct_project_f64(const cbct_plan *p, const double *f, double *y, void *stream);

@@ -393,6 +393,25 @@ def kernel_times():
     return out
 
 
+def log_counts(counts, i0=None, flat=None, min_count: float = 1.0, out=None):
+    """Line integrals from detector counts (float32 device tensors):
+    ln(ref / max(counts, min_count)), ref = the flat field or i0."""
+    torch = _torch()
+    _check_tensor(counts, counts.shape, torch.float32, "counts")
+    if flat is not None:
+        _check_tensor(flat, counts.shape, torch.float32, "flat")
+    elif i0 is None:
+        raise ValueError("give i0 or a flat field")
+    y = torch.empty_like(counts) if out is None else out
+    _check_tensor(y, counts.shape, torch.float32, "out")
+    with torch.cuda.device(counts.device):
+        check(_native.lib().cbct_log_counts(_ptr(counts), _ptr(flat) if flat is not None else None,
+                                            float(i0 or 0.0), float(min_count), _ptr(y),
+                                            int(counts.numel()), _stream_of(counts)),
+              "cbct_log_counts")
+    return y
+
+
 def probe_fma_rate(fp64: bool = False) -> float:
     """Sustained non-packed FMA rate of the current device in TFLOP/s
     (float32, or float64 with fp64=True): the measured ALU ceiling."""

@@ -445,6 +445,17 @@ extern "C" int cbct_backproject_eq2(const cbct_plan *p, const float *y, float *f
                      "eq2 kernel");
 }
 
+extern "C" int cbct_log_counts(const float *counts, const float *flat, double i0,
+                               double min_count, float *y, int64_t n, void *stream) {
+    if (!counts || !y) return set_error(CBCT_EINVAL, "NULL argument");
+    if (n < 0 || (double)n > 1.0e15) return set_error(CBCT_EINVAL, "bad element count");
+    if (!(min_count > 0) || !isfinite(min_count)) return set_error(CBCT_EINVAL, "min_count must be > 0");
+    if (!flat && (!(i0 > 0) || !isfinite(i0))) return set_error(CBCT_EINVAL, "i0 must be > 0");
+    hipStream_t s = as_stream(stream);
+    return check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_log_counts(counts, flat, i0, min_count, y, (long long)n, s); }),
+                     "log counts");
+}
+
 extern "C" int cbct_project_f64(const cbct_plan *p, const double *f, double *y, void *stream) {
     return project_impl<double>(p, f, nullptr, y, nullptr, as_stream(stream));
 }

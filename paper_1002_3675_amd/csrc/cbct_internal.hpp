@@ -126,6 +126,8 @@ size_t tv_energy_partials_count(const GridConst &gc);
 hipError_t launch_sumsq(const float *x, size_t n, double *partials, int *n_partials,
                         hipStream_t s);
 hipError_t launch_fill(float *x, size_t n, float v, hipStream_t s);
+hipError_t launch_log_counts(const float *counts, const float *flat, double i0,
+                             double min_count, float *y, long long n, hipStream_t s);
 // FMA-rate probe: blocks x 256 lanes, iters x 8 FMAs each, into out
 // (blocks x 256 elements of float, or of double when fp64)
 hipError_t launch_probe_fma(bool fp64, void *out, int blocks, int iters, hipStream_t s);

@@ -177,6 +177,25 @@ hipError_t launch_probe_fma(bool fp64, void *out, int blocks, int iters, hipStre
     return hipGetLastError();
 }
 
+// y = ln(ref / max(c, min_count)), ref = flat[i] or i0; double arithmetic.
+__global__ __launch_bounds__(256) void k_log_counts(const float *__restrict__ counts,
+                                                    const float *__restrict__ flat, double i0,
+                                                    double min_count, float *y, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double c = fmax((double)counts[i], min_count);
+    const double ref = flat ? (double)flat[i] : i0;
+    y[i] = (float)log(ref / c);
+}
+
+hipError_t launch_log_counts(const float *counts, const float *flat, double i0,
+                             double min_count, float *y, long long n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_log_counts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, counts,
+                       flat, i0, min_count, y, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(float *x, size_t n, float v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill, dim3(grid_for((long long)n)), dim3(256), 0, s, x, (long long)n, v);
     return hipGetLastError();
