@@ -52,7 +52,11 @@ extern "C" {
 
 /* Scan and grid description.  `angles` is a host array of n_views radians
  * or NULL; it is copied at plan creation.  step is the ray sample spacing
- * Delta in mm; step <= 0 selects half the smallest voxel spacing. */
+ * Delta in mm; step <= 0 selects half the smallest voxel spacing.
+ * u_off, v_off shift the detector in its own plane (mm, along e_u and
+ * e_v): pixel (i, j) is centred at u = (i - (nu-1)/2) au + u_off,
+ * v = (j - (nv-1)/2) av + v_off (u_off != 0 for half-fan scans); zero by
+ * default. */
 typedef struct cbct_geom {
     int32_t nx, ny, nz;
     double hx, hy, hz;
@@ -62,6 +66,7 @@ typedef struct cbct_geom {
     int32_t n_views;
     const double *angles;
     double step;
+    double u_off, v_off;
 } cbct_geom;
 
 typedef struct cbct_plan cbct_plan;

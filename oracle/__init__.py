@@ -100,7 +100,8 @@ def _f64(a):
 
 def _pack(g):
     dims = np.array([g.nx, g.ny, g.nz, g.nu, g.nv, g.n_views], dtype=np.int32)
-    par = np.array([g.hx, g.hy, g.hz, g.au, g.av, g.sad, g.sdd, g.step], dtype=np.float64)
+    par = np.array([g.hx, g.hy, g.hz, g.au, g.av, g.sad, g.sdd, g.step,
+                    getattr(g, "u_off", 0.0), getattr(g, "v_off", 0.0)], dtype=np.float64)
     ang = None if getattr(g, "angles", None) is None else _f64(g.angles)
     return dims, par, ang
 

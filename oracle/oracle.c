@@ -43,7 +43,8 @@
  *
  * Parameter packing used by every entry point:
  *   dims[6] = {nx, ny, nz, nu, nv, n_views}
- *   par[8]  = {hx, hy, hz, au, av, sad, sdd, step}   (step <= 0: half the
+ *   par[10] = {hx, hy, hz, au, av, sad, sdd, step, u_off, v_off}
+ *             (step <= 0: half the
  *             smallest voxel spacing)
  *   angles  = n_views radians, or NULL for 2*pi*k/n_views.
  * Volumes are [nz][ny][nx] (x fastest); projections [n_views][nv][nu].
@@ -60,6 +61,7 @@
 typedef struct {
     int nx, ny, nz, nu, nv, nviews;
     double hx, hy, hz, au, av, sad, sdd, step;
+    double u_off, v_off;  /* detector shift in its plane (mm) */
     const double *angles;
 } geom_t;
 
@@ -71,6 +73,8 @@ static geom_t unpack(const int *dims, const double *par, const double *angles)
     g.hx = par[0]; g.hy = par[1]; g.hz = par[2];
     g.au = par[3]; g.av = par[4]; g.sad = par[5]; g.sdd = par[6];
     g.step = par[7];
+    g.u_off = par[8];
+    g.v_off = par[9];
     if (g.step <= 0.0) {
         double m = g.hx;
         if (g.hy < m) m = g.hy;
@@ -93,8 +97,8 @@ static double view_angle(const geom_t *g, int k)
 static void ray_of(const geom_t *g, int k, int i, int j, double s[3], double e[3])
 {
     double th = view_angle(g, k), c = cos(th), sn = sin(th);
-    double u = ((double)i - 0.5 * (g->nu - 1)) * g->au;
-    double v = ((double)j - 0.5 * (g->nv - 1)) * g->av;
+    double u = ((double)i - 0.5 * (g->nu - 1)) * g->au + g->u_off;
+    double v = ((double)j - 0.5 * (g->nv - 1)) * g->av + g->v_off;
     double d[3];
     s[0] = g->sad * sn;  s[1] = -g->sad * c;  s[2] = 0.0;
     /* detector point = centre R(th)(0, SDD-SAD, 0) + u*R(th)(1,0,0) + v*z */
@@ -184,7 +188,8 @@ void or_eq2_backproject(const int *dims, const double *par, const double *angles
             double l2 = wx * wx + wy * wy + wz * wz;
             double L = sqrt(g.sdd * g.sdd + us * us + vs * vs);
             double w = L * L * L / (g.sdd * l2);
-            double fi = us / g.au + 0.5 * (g.nu - 1), fj = vs / g.av + 0.5 * (g.nv - 1);
+            double fi = (us - g.u_off) / g.au + 0.5 * (g.nu - 1);
+            double fj = (vs - g.v_off) / g.av + 0.5 * (g.nv - 1);
             double i0 = floor(fi), j0 = floor(fj), a = fi - i0, b = fj - j0;
             const double *yt = y + (long)t * g.nu * g.nv;
             double val = 0.0;
@@ -630,20 +635,21 @@ int or_fbs_solve(const int *dims, const double *par, const double *angles,
     geom_t g = unpack(dims, par, angles);
     if (n_levels < 1 || n_levels > 2) return -1;
     int ldims[2][6];
-    double lpar[2][8];
+    double lpar[2][10];
     const double *lY[2];
     double *lf[2];
     double *ycoarse = NULL, *fcoarse = NULL;
     int fine = n_levels - 1;
     memcpy(ldims[fine], dims, sizeof(int) * 6);
-    double fpar[8] = {g.hx, g.hy, g.hz, g.au, g.av, g.sad, g.sdd, g.step};
+    double fpar[10] = {g.hx, g.hy, g.hz, g.au, g.av, g.sad, g.sdd, g.step, g.u_off, g.v_off};
     memcpy(lpar[fine], fpar, sizeof(fpar));
     lY[fine] = Y;
     lf[fine] = f;
     if (n_levels == 2) {
         if ((g.nx | g.ny | g.nz | g.nu | g.nv) & 1) return -1;
         int cd[6] = {g.nx / 2, g.ny / 2, g.nz / 2, g.nu / 2, g.nv / 2, g.nviews};
-        double cp[8] = {2 * g.hx, 2 * g.hy, 2 * g.hz, 2 * g.au, 2 * g.av, g.sad, g.sdd, 2 * g.step};
+        double cp[10] = {2 * g.hx, 2 * g.hy, 2 * g.hz, 2 * g.au, 2 * g.av, g.sad, g.sdd,
+                         2 * g.step, g.u_off, g.v_off};
         memcpy(ldims[0], cd, sizeof(cd));
         memcpy(lpar[0], cp, sizeof(cp));
         ycoarse = (double *)malloc(sizeof(double) * (size_t)cd[3] * cd[4] * cd[5]);

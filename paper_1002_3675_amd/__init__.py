@@ -48,6 +48,8 @@ class Geometry:
     n_views: int
     angles: Optional[Tuple[float, ...]] = None
     step: float = 0.0
+    u_off: float = 0.0
+    v_off: float = 0.0
 
     @staticmethod
     def of(g) -> "Geometry":
@@ -57,7 +59,8 @@ class Geometry:
                         float(g.hz), int(g.nu), int(g.nv), float(g.au), float(g.av),
                         float(g.sad), float(g.sdd), int(g.n_views),
                         None if ang is None else tuple(float(a) for a in ang),
-                        float(getattr(g, "step", 0.0)))
+                        float(getattr(g, "step", 0.0)), float(getattr(g, "u_off", 0.0)),
+                        float(getattr(g, "v_off", 0.0)))
 
     @property
     def vol_shape(self):
@@ -72,7 +75,7 @@ def _to_c(g: Geometry):
     """cbct_geom plus the angle buffer that must outlive the call."""
     ang = None
     c = cbct_geom(g.nx, g.ny, g.nz, g.hx, g.hy, g.hz, g.nu, g.nv, g.au, g.av, g.sad, g.sdd,
-                  g.n_views, None, g.step)
+                  g.n_views, None, g.step, g.u_off, g.v_off)
     if g.angles is not None:
         ang = (ctypes.c_double * g.n_views)(*g.angles)
         c.angles = ctypes.cast(ang, ctypes.POINTER(ctypes.c_double))

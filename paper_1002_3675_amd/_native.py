@@ -25,7 +25,7 @@ class cbct_geom(ctypes.Structure):
                 ("au", ctypes.c_double), ("av", ctypes.c_double),
                 ("sad", ctypes.c_double), ("sdd", ctypes.c_double),
                 ("n_views", ctypes.c_int32), ("angles", ctypes.POINTER(ctypes.c_double)),
-                ("step", ctypes.c_double)]
+                ("step", ctypes.c_double), ("u_off", ctypes.c_double), ("v_off", ctypes.c_double)]
 
 
 class cbct_fbs_params(ctypes.Structure):

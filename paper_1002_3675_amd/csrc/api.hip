@@ -237,6 +237,8 @@ int validate_geom(const cbct_geom *g) {
         return set_error(CBCT_EINVAL, "grid dimension above 32000");
     if (std::ceil(g->nu / 32.0) * std::ceil(g->nv / 8.0) * g->n_views > 2147483647.0)
         return set_error(CBCT_EINVAL, "too many detector tiles");
+    if (!isfinite(g->u_off) || !isfinite(g->v_off))
+        return set_error(CBCT_EINVAL, "non-finite detector offset");
     if (g->angles)
         for (int k = 0; k < g->n_views; ++k)
             if (!isfinite(g->angles[k])) return set_error(CBCT_EINVAL, "non-finite angle");
@@ -308,8 +310,8 @@ extern "C" int cbct_plan_create(const cbct_geom *gin, cbct_plan **out) {
             v.snd = sn;
         }
         DetConst &d = p->det;
-        d.u0d = -0.5 * (g.nu - 1) * g.au;
-        d.v0d = -0.5 * (g.nv - 1) * g.av;
+        d.u0d = -0.5 * (g.nu - 1) * g.au + g.u_off;
+        d.v0d = -0.5 * (g.nv - 1) * g.av + g.v_off;
         d.aud = g.au;
         d.avd = g.av;
         d.sdd2d = g.sdd * g.sdd;

@@ -19,6 +19,8 @@ class Geometry:
     n_views: number of projections; angles: optional explicit angles (rad),
     default equally spaced over a full rotation.
     step: ray sample spacing (mm); 0 selects half the smallest voxel spacing.
+    u_off, v_off: detector shift in its plane (mm); u_off != 0 is a
+    half-fan (offset-detector) scan.
     """
 
     nx: int
@@ -36,6 +38,8 @@ class Geometry:
     n_views: int
     angles: Optional[Tuple[float, ...]] = None
     step: float = 0.0
+    u_off: float = 0.0
+    v_off: float = 0.0
 
     @property
     def vol_shape(self):

@@ -69,8 +69,8 @@ def ray_directions(g: Geometry, theta: float):
     det_c = np.array([-(g.sdd - g.sad) * s, (g.sdd - g.sad) * c, 0.0])
     e_u = np.array([c, s, 0.0])
     e_v = np.array([0.0, 0.0, 1.0])
-    u = (np.arange(g.nu) - (g.nu - 1) / 2.0) * g.au
-    v = (np.arange(g.nv) - (g.nv - 1) / 2.0) * g.av
+    u = (np.arange(g.nu) - (g.nu - 1) / 2.0) * g.au + g.u_off
+    v = (np.arange(g.nv) - (g.nv - 1) / 2.0) * g.av + g.v_off
     d = det_c[None, None, :] + u[None, :, None] * e_u + v[:, None, None] * e_v
     dirs = d - src
     dirs /= np.linalg.norm(dirs, axis=-1, keepdims=True)
