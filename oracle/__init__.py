@@ -6,8 +6,9 @@ no code with the HIP path.  The arithmetic lives in ``oracle.c`` (plain C99 +
 OpenMP, double precision); this module builds it with gcc on first use and
 wraps it with ctypes.  Inputs are numpy arrays (converted to float64) and a
 geometry object with the attributes nx, ny, nz, hx, hy, hz, nu, nv, au, av,
-sad, sdd, n_views, angles (None or a sequence) and step (<= 0 for half the
-smallest voxel spacing).
+sad, sdd, n_views, angles (None or a sequence), step (<= 0 for half the
+smallest voxel spacing) and, optionally, the detector shift u_off, v_off and
+the volume centre x_off, y_off, z_off (mm, default 0).
 
 Parity status: every function here is pinned by tests/test_oracle_*.py against
 closed forms, brute force or textbook special cases, except the end-to-end
@@ -76,7 +77,10 @@ def _load():
             lib.or_default_inner.restype = ctypes.c_int
             lib.or_fbs_solve.argtypes = [_I, _D, _D, _D, _D, ctypes.c_double, ctypes.c_int,
                                          _I, _D, ctypes.c_double, _I, ctypes.c_double,
-                                         ctypes.c_int, ctypes.c_int, _D, _D, _D]
+                                         ctypes.c_double, ctypes.c_int, ctypes.c_int, _D, _D,
+                                         _D, _D]
+            lib.or_coarse.argtypes = [_I, _D, _I, _D]
+            lib.or_coarse.restype = ctypes.c_int
             lib.or_fbs_solve.restype = ctypes.c_int
             lib.or_eq2_backproject.argtypes = [_I, _D, _D, _D, _D]
             lib.or_threads.argtypes = []
@@ -100,8 +104,9 @@ def _f64(a):
 
 def _pack(g):
     dims = np.array([g.nx, g.ny, g.nz, g.nu, g.nv, g.n_views], dtype=np.int32)
-    par = np.array([g.hx, g.hy, g.hz, g.au, g.av, g.sad, g.sdd, g.step,
-                    getattr(g, "u_off", 0.0), getattr(g, "v_off", 0.0)], dtype=np.float64)
+    par = np.array([g.hx, g.hy, g.hz, g.au, g.av, g.sad, g.sdd, g.step]
+                   + [float(getattr(g, k, 0.0))
+                      for k in ("u_off", "v_off", "x_off", "y_off", "z_off")], dtype=np.float64)
     ang = None if getattr(g, "angles", None) is None else _f64(g.angles)
     return dims, par, ang
 
@@ -285,20 +290,33 @@ def prolong(fc, fine_shape):
 
 
 def coarse_geometry(g):
-    """The coarse level of the two-level schedule (a plain namespace)."""
+    """Geometry of the next coarser multigrid level (a plain namespace):
+    half the voxels and pixels per axis, spacings, pitches and step doubled,
+    cells and pixels at the centres of the blocks they average."""
     import types
+    dims, par, _ = _pack(g)
+    cd = np.zeros(6, dtype=np.int32)
+    cp = np.zeros(13)
+    if _load().or_coarse(dims.ctypes.data_as(_I), _dp(par), cd.ctypes.data_as(_I), _dp(cp)):
+        raise ValueError("oracle coarse_geometry: a size would fall below 1")
     return types.SimpleNamespace(
-        nx=g.nx // 2, ny=g.ny // 2, nz=g.nz // 2, hx=2 * g.hx, hy=2 * g.hy, hz=2 * g.hz,
-        nu=g.nu // 2, nv=g.nv // 2, au=2 * g.au, av=2 * g.av, sad=g.sad, sdd=g.sdd,
-        n_views=g.n_views, angles=getattr(g, "angles", None), step=2 * step_of(g))
+        nx=int(cd[0]), ny=int(cd[1]), nz=int(cd[2]), hx=cp[0], hy=cp[1], hz=cp[2],
+        nu=int(cd[3]), nv=int(cd[4]), au=cp[3], av=cp[4], sad=cp[5], sdd=cp[6],
+        n_views=g.n_views, angles=getattr(g, "angles", None),
+        step=cp[7], u_off=cp[8], v_off=cp[9],
+        x_off=cp[10], y_off=cp[11], z_off=cp[12])
 
 
 def fbs_solve(g, Y, mu, iters, f0=None, beta=None, eps=1e-3, n_inner=None,
-              tv_weight=1.0, clip_mode=0, trace=False, gradient="matched"):
+              tv_weight=1.0, clip_mode=0, trace=False, gradient="matched", tol=0.0):
     """Algorithm A1 with the coarse-to-fine schedule.
 
-    iters: outer iterations per level, coarse first (length 1 or 2).
-    Returns dict(f, used_beta, used_inner, report=(E, E_eps, E1, E2), trace).
+    iters: outer iterations per level, coarse first (1 to 4 levels); with
+    tol > 0 a level stops after the first iteration whose relative change
+    ||f_{k+1} - f_k|| / ||f_{k+1}|| is <= tol, and iters are maxima.
+    Returns dict(f, used_beta, used_inner, used_iters, change (last relative
+    change per level), report=(E, E_eps, E1, E2), trace (packed rows:
+    used_iters[l] + 1 per level)).
     """
     lib = _load()
     dims, par, ang = _pack(g)
@@ -308,14 +326,18 @@ def fbs_solve(g, Y, mu, iters, f0=None, beta=None, eps=1e-3, n_inner=None,
     it = np.array(iters, dtype=np.int32)
     b = np.zeros(nl) if beta is None else _f64(beta)
     k = np.zeros(nl, dtype=np.int32) if n_inner is None else np.array(n_inner, dtype=np.int32)
-    used = np.zeros(4)
+    used = np.zeros(3 * nl)
+    change = np.zeros(nl)
     tr = np.zeros((int(sum(iters)) + nl, 4)) if trace else None
     rep = np.zeros(4)
     gm = {"matched": 0, "eq2": 1}[gradient]
     rc = lib.or_fbs_solve(dims.ctypes.data_as(_I), _dp(par), _dp(ang), _dp(Y), _dp(f), mu, nl,
-                          it.ctypes.data_as(_I), _dp(b), eps, k.ctypes.data_as(_I), tv_weight,
-                          clip_mode, gm, _dp(used), _dp(tr), _dp(rep))
+                          it.ctypes.data_as(_I), _dp(b), eps, k.ctypes.data_as(_I), tol,
+                          tv_weight, clip_mode, gm, _dp(used), _dp(change), _dp(tr), _dp(rep))
     if rc != 0:
         raise ValueError("oracle fbs_solve: invalid arguments")
-    return dict(f=f, used_beta=used[:nl].copy(), used_inner=used[2:2 + nl].astype(int),
-                report=rep, trace=tr)
+    made = used[2 * nl:].astype(int)
+    if tr is not None:
+        tr = tr[:int(made.sum()) + nl]
+    return dict(f=f, used_beta=used[:nl].copy(), used_inner=used[nl:2 * nl].astype(int),
+                used_iters=made, change=change, report=rep, trace=tr)

@@ -37,15 +37,25 @@
  *   beta   1.1 * mu * (2 N_vox/N_meas) * lambda, lambda from power
  *          iteration on P^T P started from the all-ones vector, unless the
  *          caller gives beta.
- *   multi-grid  two levels: half the voxels per axis (spacing doubled),
- *          2x2-binned detector (pitch doubled), step doubled; the coarse
- *          result is prolonged trilinearly (cell-centred) to the fine grid.
+ *   multi-grid  up to four levels, cascadic: each coarser level has half
+ *          the voxels per axis (spacing doubled, 2x2x2 block means), a
+ *          2x2-binned detector (pitch doubled) and the step doubled; its
+ *          cells and pixels sit at the centres of the blocks and pixel
+ *          pairs they average (a half fine pitch off the axis when a size
+ *          is odd, the last fine plane then left out); each level's result
+ *          is prolonged trilinearly (cell-centred) to the next finer grid.
+ *   stopping  fixed outer counts per level, or, with tol > 0, a level
+ *          stops after the first iteration with
+ *          ||f_{k+1} - f_k||_2 <= tol * ||f_{k+1}||_2 (the count is then a
+ *          maximum).
  *
  * Parameter packing used by every entry point:
  *   dims[6] = {nx, ny, nz, nu, nv, n_views}
- *   par[10] = {hx, hy, hz, au, av, sad, sdd, step, u_off, v_off}
- *             (step <= 0: half the
- *             smallest voxel spacing)
+ *   par[13] = {hx, hy, hz, au, av, sad, sdd, step, u_off, v_off,
+ *              x_off, y_off, z_off}
+ *             (step <= 0: half the smallest voxel spacing; u_off, v_off
+ *             shift the detector in its plane, x_off, y_off, z_off the
+ *             volume centre, in mm)
  *   angles  = n_views radians, or NULL for 2*pi*k/n_views.
  * Volumes are [nz][ny][nx] (x fastest); projections [n_views][nv][nu].
  */
@@ -62,6 +72,7 @@ typedef struct {
     int nx, ny, nz, nu, nv, nviews;
     double hx, hy, hz, au, av, sad, sdd, step;
     double u_off, v_off;  /* detector shift in its plane (mm) */
+    double off[3];        /* volume centre (mm) */
     const double *angles;
 } geom_t;
 
@@ -75,6 +86,9 @@ static geom_t unpack(const int *dims, const double *par, const double *angles)
     g.step = par[7];
     g.u_off = par[8];
     g.v_off = par[9];
+    g.off[0] = par[10];
+    g.off[1] = par[11];
+    g.off[2] = par[12];
     if (g.step <= 0.0) {
         double m = g.hx;
         if (g.hy < m) m = g.hy;
@@ -112,7 +126,7 @@ static void ray_of(const geom_t *g, int k, int i, int j, double s[3], double e[3
 
 /* Range of sample indices n with n*step inside the ray's intersection with
  * the box on which the zero-padded trilinear interpolant can be non-zero,
- * |x_a| <= (N_a + 1) h_a / 2.  Returns 0 when the ray misses the box. */
+ * |x_a - off_a| <= (N_a + 1) h_a / 2.  Returns 0 when the ray misses it. */
 static int sample_range(const geom_t *g, const double s[3], const double e[3],
                         long *n0, long *n1)
 {
@@ -121,10 +135,11 @@ static int sample_range(const geom_t *g, const double s[3], const double e[3],
     double tin = -INFINITY, tout = INFINITY;
     for (int a = 0; a < 3; ++a) {
         if (e[a] == 0.0) {
-            if (s[a] <= -half[a] || s[a] >= half[a]) return 0;
+            if (s[a] <= g->off[a] - half[a] || s[a] >= g->off[a] + half[a]) return 0;
             continue;
         }
-        double t1 = (-half[a] - s[a]) / e[a], t2 = (half[a] - s[a]) / e[a];
+        double t1 = (g->off[a] - half[a] - s[a]) / e[a];
+        double t2 = (g->off[a] + half[a] - s[a]) / e[a];
         double lo = t1 < t2 ? t1 : t2, hi = t1 < t2 ? t2 : t1;
         if (lo > tin) tin = lo;
         if (hi < tout) tout = hi;
@@ -142,7 +157,7 @@ static void stencil(const geom_t *g, const double p[3], long idx0[3], double w[3
     double h[3] = {g->hx, g->hy, g->hz};
     int n[3] = {g->nx, g->ny, g->nz};
     for (int a = 0; a < 3; ++a) {
-        double q = p[a] / h[a] + 0.5 * (n[a] - 1);  /* voxel-index coordinate */
+        double q = (p[a] - g->off[a]) / h[a] + 0.5 * (n[a] - 1);  /* voxel-index coordinate */
         double fl = floor(q);
         idx0[a] = (long)fl;
         w[a][1] = q - fl;
@@ -173,9 +188,9 @@ void or_eq2_backproject(const int *dims, const double *par, const double *angles
 #pragma omp parallel for schedule(static)
     for (long v = 0; v < nvox; ++v) {
         long i = v % g.nx, j = (v / g.nx) % g.ny, k = v / ((long)g.nx * g.ny);
-        double x = ((double)i - 0.5 * (g.nx - 1)) * g.hx;
-        double yy = ((double)j - 0.5 * (g.ny - 1)) * g.hy;
-        double z = ((double)k - 0.5 * (g.nz - 1)) * g.hz;
+        double x = ((double)i - 0.5 * (g.nx - 1)) * g.hx + g.off[0];
+        double yy = ((double)j - 0.5 * (g.ny - 1)) * g.hy + g.off[1];
+        double z = ((double)k - 0.5 * (g.nz - 1)) * g.hz + g.off[2];
         double sum = 0.0;
         for (int t = 0; t < g.nviews; ++t) {
             double th = view_angle(&g, t), c = cos(th), sn = sin(th);
@@ -587,11 +602,28 @@ static void energies(const int *dims, const double *par, const double *angles,
     out[3] = e2;
 }
 
-/* One level of Algorithm A1: iters outer iterations on f (in place). */
-static void fbs_level(const int *dims, const double *par, const double *angles,
-                      const double *Y, double *f, double mu, double beta, double eps,
-                      int n_inner, int iters, double tv_weight, int clip_mode,
-                      int grad_mode, double *trace)
+/* Relative change ||a - b||_2 / ||a||_2 of one outer iteration (a the new
+ * iterate, b the previous one); 0 when both are zero, +inf when only a
+ * is. */
+static double rel_change(long n, const double *a, const double *b)
+{
+    double d = 0.0, m = 0.0;
+    for (long v = 0; v < n; ++v) {
+        d += (a[v] - b[v]) * (a[v] - b[v]);
+        m += a[v] * a[v];
+    }
+    if (m == 0.0) return d == 0.0 ? 0.0 : INFINITY;
+    return sqrt(d / m);
+}
+
+/* One level of Algorithm A1: at most iters outer iterations on f (in
+ * place); with tol > 0 it stops after the first iteration whose relative
+ * change is <= tol.  Returns the number of iterations made; *change gets
+ * the relative change of the last one (0 if none, or if tol <= 0). */
+static int fbs_level(const int *dims, const double *par, const double *angles,
+                     const double *Y, double *f, double mu, double beta, double eps,
+                     int n_inner, int iters, double tol, double tv_weight, int clip_mode,
+                     int grad_mode, double *trace, double *change)
 {
     geom_t g = unpack(dims, par, angles);
     long nvox = (long)g.nx * g.ny * g.nz, nmeas = (long)g.nviews * g.nu * g.nv;
@@ -600,8 +632,12 @@ static void fbs_level(const int *dims, const double *par, const double *angles,
     double *r = (double *)malloc(sizeof(double) * (size_t)nmeas);
     double *grad = (double *)malloc(sizeof(double) * (size_t)nvox);
     double *gaux = (double *)malloc(sizeof(double) * (size_t)nvox);
-    for (int it = 0; it < iters; ++it) {
+    double *prev = tol > 0.0 ? (double *)malloc(sizeof(double) * (size_t)nvox) : NULL;
+    int it = 0;
+    *change = 0.0;
+    while (it < iters) {
         if (trace) energies(dims, par, angles, f, Y, mu, eps, trace + 4 * it);
+        if (prev) memcpy(prev, f, sizeof(double) * (size_t)nvox);
         /* Step 1 (update): g = f - (mu V / beta) dE2/df */
         or_data_energy(dims, par, angles, f, Y, r);
         if (grad_mode == 1)
@@ -611,53 +647,96 @@ static void fbs_level(const int *dims, const double *par, const double *angles,
         for (long v = 0; v < nvox; ++v) gaux[v] = f[v] - tau * grad[v];
         /* Steps 2 and 3 (minimise, correct), started from the current f */
         or_tv_prox(dims, h, gaux, f, beta, eps, n_inner, 0.0, clip_mode, tv_weight, NULL);
+        ++it;
+        if (prev) {
+            *change = rel_change(nvox, f, prev);
+            if (*change <= tol) break;
+        }
     }
-    if (trace) energies(dims, par, angles, f, Y, mu, eps, trace + 4 * iters);
-    free(r); free(grad); free(gaux);
+    if (trace) energies(dims, par, angles, f, Y, mu, eps, trace + 4 * it);
+    free(r); free(grad); free(gaux); free(prev);
+    return it;
 }
+
+/* Geometry of the next coarser level: half the voxels per axis with the
+ * spacing doubled, a detector of half the pixels per axis with the pitch
+ * doubled, the step doubled.  A coarse cell is the mean of fine voxels
+ * (2i, 2i + 1) along each axis, so it is placed at their centre: on an axis
+ * of odd size that is half a fine spacing below the fine grid's centre
+ * (the last fine plane belongs to no block).  Coarse pixels likewise sit
+ * at the centres of the pixel pairs they average.  Returns -1 when a
+ * coarse size would be below 1. */
+int or_coarse(const int *dims, const double *par, int *cdims, double *cpar)
+{
+    int n[5] = {dims[0], dims[1], dims[2], dims[3], dims[4]};
+    for (int a = 0; a < 5; ++a)
+        if (n[a] / 2 < 1) return -1;
+    geom_t g = unpack(dims, par, NULL);
+    cdims[0] = n[0] / 2; cdims[1] = n[1] / 2; cdims[2] = n[2] / 2;
+    cdims[3] = n[3] / 2; cdims[4] = n[4] / 2; cdims[5] = dims[5];
+    double h[3] = {g.hx, g.hy, g.hz};
+    for (int a = 0; a < 3; ++a) cpar[a] = 2.0 * h[a];
+    cpar[3] = 2.0 * g.au;
+    cpar[4] = 2.0 * g.av;
+    cpar[5] = g.sad;
+    cpar[6] = g.sdd;
+    cpar[7] = 2.0 * g.step;
+    cpar[8] = g.u_off - 0.5 * g.au * (double)(n[3] & 1);
+    cpar[9] = g.v_off - 0.5 * g.av * (double)(n[4] & 1);
+    for (int a = 0; a < 3; ++a) cpar[10 + a] = g.off[a] - 0.5 * h[a] * (double)(n[a] & 1);
+    return 0;
+}
+
+#define OR_MAX_LEVELS 4
 
 /* Full solve with the coarse-to-fine schedule.
  *   Y: [n_views][nv][nu] fine data; f: fine volume, in = f0, out = result.
- *   n_levels 1 or 2; iters[level] outer iterations (coarse first);
+ *   n_levels 1..4; iters[level] outer iterations (coarse first), a
+ *   maximum when tol > 0;
  *   beta[level] <= 0 -> 1.1*mu*(2 N_vox/N_meas)*lambda (30 power steps);
  *   n_inner[level] <= 0 -> or_default_inner.
- *   used[0..3] (optional) receive beta and n_inner per level.
- *   trace (optional): rows of (E, E_eps, E1, E2), iters[l]+1 rows per level.
+ *   used (optional, 3 * n_levels): beta, n_inner and iterations made per
+ *   level; change (optional, n_levels): relative change of each level's
+ *   last iteration (tol > 0).
+ *   trace (optional): rows of (E, E_eps, E1, E2), packed: (iterations
+ *   made + 1) rows per level, coarse first.
  *   report (optional): E, E_eps, E1, E2 of the returned f (fine level).
  *   grad_mode 0: Step 1 with the matched transpose; 1: with Eq. (2).
  * Returns 0, or -1 on invalid sizes. */
 int or_fbs_solve(const int *dims, const double *par, const double *angles,
                  const double *Y, double *f, double mu, int n_levels,
                  const int *iters, const double *beta, double eps,
-                 const int *n_inner, double tv_weight, int clip_mode, int grad_mode,
-                 double *used, double *trace, double *report)
+                 const int *n_inner, double tol, double tv_weight, int clip_mode,
+                 int grad_mode, double *used, double *change, double *trace,
+                 double *report)
 {
-    geom_t g = unpack(dims, par, angles);
-    if (n_levels < 1 || n_levels > 2) return -1;
-    int ldims[2][6];
-    double lpar[2][10];
-    const double *lY[2];
-    double *lf[2];
-    double *ycoarse = NULL, *fcoarse = NULL;
+    if (n_levels < 1 || n_levels > OR_MAX_LEVELS) return -1;
+    int ldims[OR_MAX_LEVELS][6];
+    double lpar[OR_MAX_LEVELS][13];
+    const double *lY[OR_MAX_LEVELS];
+    double *lf[OR_MAX_LEVELS];
+    double *owned[2 * OR_MAX_LEVELS] = {NULL};
     int fine = n_levels - 1;
+    geom_t g = unpack(dims, par, angles);
+    double fpar[13] = {g.hx, g.hy, g.hz, g.au, g.av, g.sad, g.sdd, g.step, g.u_off, g.v_off,
+                       g.off[0], g.off[1], g.off[2]};
     memcpy(ldims[fine], dims, sizeof(int) * 6);
-    double fpar[10] = {g.hx, g.hy, g.hz, g.au, g.av, g.sad, g.sdd, g.step, g.u_off, g.v_off};
     memcpy(lpar[fine], fpar, sizeof(fpar));
     lY[fine] = Y;
     lf[fine] = f;
-    if (n_levels == 2) {
-        if ((g.nx | g.ny | g.nz | g.nu | g.nv) & 1) return -1;
-        int cd[6] = {g.nx / 2, g.ny / 2, g.nz / 2, g.nu / 2, g.nv / 2, g.nviews};
-        double cp[10] = {2 * g.hx, 2 * g.hy, 2 * g.hz, 2 * g.au, 2 * g.av, g.sad, g.sdd,
-                         2 * g.step, g.u_off, g.v_off};
-        memcpy(ldims[0], cd, sizeof(cd));
-        memcpy(lpar[0], cp, sizeof(cp));
-        ycoarse = (double *)malloc(sizeof(double) * (size_t)cd[3] * cd[4] * cd[5]);
-        fcoarse = (double *)malloc(sizeof(double) * (size_t)cd[0] * cd[1] * cd[2]);
-        or_bin_detector(g.nu, g.nv, g.nviews, Y, ycoarse);
-        or_restrict(dims, f, fcoarse);
-        lY[0] = ycoarse;
-        lf[0] = fcoarse;
+    for (int l = fine - 1; l >= 0; --l)
+        if (or_coarse(ldims[l + 1], lpar[l + 1], ldims[l], lpar[l])) return -1;
+    /* data and start of every coarser level from the next finer one */
+    for (int l = fine - 1; l >= 0; --l) {
+        const int *d = ldims[l], *D = ldims[l + 1];
+        double *yc = (double *)malloc(sizeof(double) * (size_t)d[3] * d[4] * d[5]);
+        double *fc = (double *)malloc(sizeof(double) * (size_t)d[0] * d[1] * d[2]);
+        owned[2 * l] = yc;
+        owned[2 * l + 1] = fc;
+        or_bin_detector(D[3], D[4], D[5], lY[l + 1], yc);
+        or_restrict(D, lf[l + 1], fc);
+        lY[l] = yc;
+        lf[l] = fc;
     }
     double *tr = trace;
     for (int l = 0; l < n_levels; ++l) {
@@ -670,15 +749,20 @@ int or_fbs_solve(const int *dims, const double *par, const double *angles,
             b = 1.1 * mu * 2.0 * (double)nvox / (double)nmeas * or_power_lambda(d, p, angles, 30);
         int k = n_inner ? n_inner[l] : 0;
         if (k <= 0) k = or_default_inner(h, b, eps);
-        if (used) { used[l] = b; used[2 + l] = (double)k; }
-        fbs_level(d, p, angles, lY[l], lf[l], mu, b, eps, k, iters[l], tv_weight,
-                  clip_mode, grad_mode, tr);
-        if (tr) tr += 4 * (iters[l] + 1);
-        if (l == 0 && n_levels == 2) or_prolong(ldims[0], dims, fcoarse, f);
+        double ch = 0.0;
+        int made = fbs_level(d, p, angles, lY[l], lf[l], mu, b, eps, k, iters[l], tol,
+                             tv_weight, clip_mode, grad_mode, tr, &ch);
+        if (used) {
+            used[l] = b;
+            used[n_levels + l] = (double)k;
+            used[2 * n_levels + l] = (double)made;
+        }
+        if (change) change[l] = ch;
+        if (tr) tr += 4 * (made + 1);
+        if (l < fine) or_prolong(ldims[l], ldims[l + 1], lf[l], lf[l + 1]);
     }
     if (report) energies(dims, fpar, angles, f, Y, mu, eps, report);
-    free(ycoarse);
-    free(fcoarse);
+    for (int q = 0; q < 2 * OR_MAX_LEVELS; ++q) free(owned[q]);
     return 0;
 }
 

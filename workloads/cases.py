@@ -76,9 +76,9 @@ def fov_mask(g: Geometry) -> np.ndarray:
     axial range seen by every view (boolean, (nz, ny, nx))."""
     half_u = g.nu * g.au / 2.0
     fov_r = g.sad * half_u / math.hypot(g.sdd, half_u)
-    x = (np.arange(g.nx) - (g.nx - 1) / 2.0) * g.hx
-    y = (np.arange(g.ny) - (g.ny - 1) / 2.0) * g.hy
-    z = (np.arange(g.nz) - (g.nz - 1) / 2.0) * g.hz
+    x = (np.arange(g.nx) - (g.nx - 1) / 2.0) * g.hx + g.x_off
+    y = (np.arange(g.ny) - (g.ny - 1) / 2.0) * g.hy + g.y_off
+    z = (np.arange(g.nz) - (g.nz - 1) / 2.0) * g.hz + g.z_off
     r = np.sqrt(x[None, :] ** 2 + y[:, None] ** 2)
     half_v = g.nv * g.av / 2.0
     zmax = half_v * (g.sad - r) / g.sdd

@@ -21,6 +21,8 @@ class Geometry:
     step: ray sample spacing (mm); 0 selects half the smallest voxel spacing.
     u_off, v_off: detector shift in its plane (mm); u_off != 0 is a
     half-fan (offset-detector) scan.
+    x_off, y_off, z_off: centre of the voxel grid (mm); 0 puts it on the
+    rotation axis, level with the source.
     """
 
     nx: int
@@ -40,6 +42,9 @@ class Geometry:
     step: float = 0.0
     u_off: float = 0.0
     v_off: float = 0.0
+    x_off: float = 0.0
+    y_off: float = 0.0
+    z_off: float = 0.0
 
     @property
     def vol_shape(self):

@@ -98,9 +98,9 @@ def voxelise(g: Geometry, phantom: Sequence[Ellipsoid], sub: int = 0) -> np.ndar
         sub = 4 if g.n_vox <= 128 ** 3 else 2
     out = np.zeros(g.vol_shape, dtype=np.float64)
     offs = (np.arange(sub) + 0.5) / sub - 0.5
-    cx = (np.arange(g.nx) - (g.nx - 1) / 2.0) * g.hx
-    cy = (np.arange(g.ny) - (g.ny - 1) / 2.0) * g.hy
-    cz = (np.arange(g.nz) - (g.nz - 1) / 2.0) * g.hz
+    cx = (np.arange(g.nx) - (g.nx - 1) / 2.0) * g.hx + g.x_off
+    cy = (np.arange(g.ny) - (g.ny - 1) / 2.0) * g.hy + g.y_off
+    cz = (np.arange(g.nz) - (g.nz - 1) / 2.0) * g.hz + g.z_off
     for e in phantom:
         r = e.rotation()
         ext = np.abs(r) @ np.asarray(e.axes)  # half-extent of the bounding box
