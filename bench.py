@@ -330,6 +330,36 @@ def lowdose_sweep(torch, cb):
     return rows
 
 
+def multigrid_schedules(torch, cb, plan, case, Y):
+    """The head solve under other schedules: fine level only, deeper
+    cascadic multigrid (3 and 4 levels) with fixed counts, and the
+    relative-change stopping rule with generous maxima.  Each row gives the
+    iterations made per level, the time, the final energy E and the
+    relative L2 error to the voxelised phantom over the field of view."""
+    import numpy as np
+    from workloads import fov_mask, voxelise
+    g = case.geom
+    truth = voxelise(g, case.phantom, sub=2)
+    mask = fov_mask(g)
+    rows = []
+    for iters, tol in (((40,), 0.0), ((20, 20), 0.0), ((20, 20, 20), 0.0),
+                       ((20, 20, 20, 20), 0.0), ((60, 60, 60), 3e-3), ((60, 60, 60), 1e-3)):
+        p = cb.FbsParams(mu=case.mu, iters=iters, eps=case.eps, trace_energy=True, tol=tol)
+        cb.fbs_solve(plan, Y, p)  # beta of any new level, cached in its plan
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f, rep = cb.fbs_solve(plan, Y, p)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        fn = f.cpu().double().numpy()
+        err = np.linalg.norm((fn - truth)[mask]) / np.linalg.norm(truth[mask])
+        rows.append({"iters": list(iters), "tol": tol, "level_iters": list(rep.level_iters),
+                     "solve_s": dt, "E": rep.E, "rel_l2_fov": err})
+        log("schedule %s tol %g: made %s, %.3f s, E %.6e, fov %.4f"
+            % (iters, tol, rep.level_iters, dt, rep.E, err))
+    return rows
+
+
 def tiny_recon_times(torch, cb):
     """Seconds per reconstruction of the 64^3 / 16-view workload (10
     iterations, beta and inner count from the oracle's rule on both sides):
@@ -467,6 +497,8 @@ def main():
     ms_p = time_op(torch, lambda: plan.project(fr, out=yb), args.ops_reps)
     ms_pt = time_op(torch, lambda: plan.backproject(yr, out=fb), args.ops_reps)
     eq2 = eq2_comparison(torch, cb, plan, Y, params, f, rep, yr, fb, ms_pt, args.ops_reps)
+    del fr, yr, yb, fb
+    schedules = multigrid_schedules(torch, cb, plan, case, Y)
 
     out = {
         "metric": METRIC,
@@ -502,6 +534,7 @@ def main():
         "alu_measured_tflops": {"fp32_fma": cb.probe_fma_rate(False),
                                 "fp64_fma": cb.probe_fma_rate(True)},
         "paper_eq2": eq2,
+        "multigrid_schedules": schedules,
         "per_kernel": per_kernel,
         "roofline": roofline,
         "paper_context": "77-130 s per reconstruction on a Tesla C1060 (different "

@@ -55,8 +55,10 @@ extern "C" {
  * Delta in mm; step <= 0 selects half the smallest voxel spacing.
  * u_off, v_off shift the detector in its own plane (mm, along e_u and
  * e_v): pixel (i, j) is centred at u = (i - (nu-1)/2) au + u_off,
- * v = (j - (nv-1)/2) av + v_off (u_off != 0 for half-fan scans); zero by
- * default. */
+ * v = (j - (nv-1)/2) av + v_off (u_off != 0 for half-fan scans).
+ * x_off, y_off, z_off place the centre of the voxel grid (mm): voxel
+ * (i, j, k) is centred at x = (i - (nx-1)/2) hx + x_off, and so on.  All
+ * shifts are zero by default; they must be finite. */
 typedef struct cbct_geom {
     int32_t nx, ny, nz;
     double hx, hy, hz;
@@ -67,6 +69,7 @@ typedef struct cbct_geom {
     const double *angles;
     double step;
     double u_off, v_off;
+    double x_off, y_off, z_off;
 } cbct_geom;
 
 typedef struct cbct_plan cbct_plan;
@@ -163,54 +166,73 @@ int cbct_tv_energy(const cbct_geom *grid, const float *f, double eps,
 int cbct_plan_lambda(const cbct_plan *p, int32_t n_iter, double *lambda_host,
                      void *stream);
 
-/* Solver parameters.  E = E1 + mu*E2.  n_levels 1, or 2 for the
- * coarse-to-fine schedule (coarse level: half the voxels per axis with
- * doubled spacing, 2x2-binned detector with doubled pitch, doubled step;
- * needs even nx, ny, nz, nu, nv).  iters[level] outer iterations, coarse
- * first.  beta[level] <= 0 selects 1.1 * mu * (2 N_vox/N_meas) * lambda
- * with lambda from 30 power-iteration steps on that level.  n_inner[level]
- * <= 0 selects min(200, ceil(3 (1 + 4 sum_a h_a^-2 / (eps beta)))).
- * eps is the TV smoothing (1/mm^2).  trace_energy = 1 computes E at the
- * start of every outer iteration and at the end (one host sync each).
- * gradient selects Step 1's gradient of E2: 0 the exact transpose of the
- * projector (cbct_backproject; then E_eps never increases), 1 the paper's
- * Eq. (2) as printed (cbct_backproject_eq2, far cheaper, not matched). */
+/* Solver parameters.  E = E1 + mu*E2.  n_levels 1..CBCT_MAX_LEVELS
+ * levels of the cascadic coarse-to-fine schedule (the paper's multigrid
+ * remark): each coarser level has half the voxels per axis with doubled
+ * spacing (2x2x2 block means of the finer start), a 2x2-binned detector
+ * with doubled pitch and a doubled step.  Its cells and pixels sit at the
+ * centres of the blocks they average: on an axis of odd size half a finer
+ * spacing (pitch) below the finer grid's centre, the last finer plane
+ * (row) belonging to no block.  Every level needs sizes >= 1.  Each
+ * level's result is prolonged trilinearly into the next finer start.
+ * iters[level] outer iterations, coarse first.  tol = 0 runs exactly
+ * that many; tol > 0 ends a level after the first outer iteration with
+ * ||f_{k+1} - f_k||_2 <= tol ||f_{k+1}||_2 (iters is then a maximum; one
+ * host sync per outer iteration to read the change).  beta[level] <= 0
+ * selects 1.1 * mu * (2 N_vox/N_meas) * lambda with lambda from 30
+ * power-iteration steps on that level.  n_inner[level] <= 0 selects
+ * min(200, ceil(3 (1 + 4 sum_a h_a^-2 / (eps beta)))).  eps is the TV
+ * smoothing (1/mm^2).  trace_energy = 1 computes E at the start of every
+ * outer iteration and at the end (one host sync each).  gradient selects
+ * Step 1's gradient of E2: 0 the exact transpose of the projector
+ * (cbct_backproject; then E_eps never increases), 1 the paper's Eq. (2)
+ * as printed (cbct_backproject_eq2, far cheaper, not matched). */
+#define CBCT_MAX_LEVELS 4
 typedef struct cbct_fbs_params {
     double mu;
     int32_t n_levels;
-    int32_t iters[2];
-    double beta[2];
+    int32_t iters[CBCT_MAX_LEVELS];
+    double beta[CBCT_MAX_LEVELS];
     double eps;
-    int32_t n_inner[2];
+    int32_t n_inner[CBCT_MAX_LEVELS];
     int32_t trace_energy;
     int32_t gradient;
+    double tol;
 } cbct_fbs_params;
 
 /* Filled by the solver.  E, E_eps, E1, E2 describe the returned volume
- * (computed only when trace_energy = 1, else zero).  trace, if not NULL,
- * is a caller HOST array of (iters[0] + 1 [+ iters[1] + 1]) rows of 4
- * doubles (E, E_eps, E1, E2) per level, filled when trace_energy = 1. */
+ * (computed only when trace_energy = 1, else zero).  level_iters[level]
+ * counts the outer iterations made on each level, iters_done their sum;
+ * change[level] is the relative change of the level's last iteration
+ * (tol > 0 only, else 0).  trace, if not NULL, is a caller HOST array of
+ * at least sum over levels of (iters[level] + 1) rows of 4 doubles
+ * (E, E_eps, E1, E2), filled when trace_energy = 1 and packed: level by
+ * level, coarse first, (level_iters[level] + 1) rows each. */
 typedef struct cbct_fbs_report {
     double E, E_eps, E1, E2;
-    double beta_used[2];
-    int32_t n_inner_used[2];
+    double beta_used[CBCT_MAX_LEVELS];
+    int32_t n_inner_used[CBCT_MAX_LEVELS];
+    int32_t level_iters[CBCT_MAX_LEVELS];
     int32_t iters_done;
+    double change[CBCT_MAX_LEVELS];
     double *trace;
 } cbct_fbs_report;
 
-/* Full solve: f holds f0 on entry (the coarse level starts from its 2x2x2
- * mean) and the result on exit; Y is the fine-level data.  Equivalent to
- * init + step(all) + free.  Synchronises `stream` before returning only
- * when tracing or estimating beta. */
+/* Full solve: f holds f0 on entry (each coarser level starts from the
+ * 2x2x2 means of the next finer start) and the result on exit; Y is the
+ * fine-level data.  Equivalent to init + step(all) + free.  Synchronises
+ * `stream` before returning only when tracing, stopping by tolerance or
+ * estimating beta. */
 int cbct_fbs_solve(const cbct_plan *fine, const float *Y, float *f,
                    const cbct_fbs_params *prm, cbct_fbs_report *rep,
                    void *stream);
 
 /* Step API for schedulers.  init validates, allocates the state (device
- * scratch for both levels), bins Y and restricts f for the coarse level.
+ * scratch for every level), bins Y and restricts f down the levels.
  * Y and f must stay valid until cbct_fbs_free.  step advances up to
- * n_iters outer iterations, moving to the fine level (prolongation) when
- * the coarse level is done; it is asynchronous unless tracing.  finished
+ * n_iters outer iterations, moving to the next finer level (prolongation)
+ * when a level is done; it is asynchronous unless tracing or stopping by
+ * tolerance.  finished
  * returns 1 when every iteration is done, 0 otherwise, and a negative code
  * for a NULL state.  report copies the report so far. */
 int cbct_fbs_init(const cbct_plan *fine, const float *Y, float *f,

@@ -50,6 +50,9 @@ class Geometry:
     step: float = 0.0
     u_off: float = 0.0
     v_off: float = 0.0
+    x_off: float = 0.0
+    y_off: float = 0.0
+    z_off: float = 0.0
 
     @staticmethod
     def of(g) -> "Geometry":
@@ -59,8 +62,9 @@ class Geometry:
                         float(g.hz), int(g.nu), int(g.nv), float(g.au), float(g.av),
                         float(g.sad), float(g.sdd), int(g.n_views),
                         None if ang is None else tuple(float(a) for a in ang),
-                        float(getattr(g, "step", 0.0)), float(getattr(g, "u_off", 0.0)),
-                        float(getattr(g, "v_off", 0.0)))
+                        float(getattr(g, "step", 0.0)),
+                        *(float(getattr(g, k, 0.0))
+                          for k in ("u_off", "v_off", "x_off", "y_off", "z_off")))
 
     @property
     def vol_shape(self):
@@ -75,7 +79,7 @@ def _to_c(g: Geometry):
     """cbct_geom plus the angle buffer that must outlive the call."""
     ang = None
     c = cbct_geom(g.nx, g.ny, g.nz, g.hx, g.hy, g.hz, g.nu, g.nv, g.au, g.av, g.sad, g.sdd,
-                  g.n_views, None, g.step, g.u_off, g.v_off)
+                  g.n_views, None, g.step, g.u_off, g.v_off, g.x_off, g.y_off, g.z_off)
     if g.angles is not None:
         ang = (ctypes.c_double * g.n_views)(*g.angles)
         c.angles = ctypes.cast(ang, ctypes.POINTER(ctypes.c_double))
@@ -270,11 +274,12 @@ class FbsParams:
     n_inner: Optional[Sequence[int]] = None  # None / <= 0 -> default rule
     trace_energy: bool = False
     gradient: str = "matched"             # "matched" (P^T) or "eq2" (the paper's Eq. (2))
+    tol: float = 0.0                      # > 0: stop a level at this relative change
 
     def to_c(self):
         n = len(self.iters)
-        if n not in (1, 2):
-            raise ValueError("iters must have 1 or 2 entries")
+        if not 1 <= n <= _native.MAX_LEVELS:
+            raise ValueError("iters must have 1 to %d entries" % _native.MAX_LEVELS)
         p = cbct_fbs_params()
         p.mu = float(self.mu)
         p.n_levels = n
@@ -287,6 +292,7 @@ class FbsParams:
         if self.gradient not in ("matched", "eq2"):
             raise ValueError("gradient must be 'matched' or 'eq2'")
         p.gradient = 1 if self.gradient == "eq2" else 0
+        p.tol = float(self.tol)
         return p
 
 
@@ -299,15 +305,20 @@ class FbsReport:
     beta_used: Tuple[float, ...]
     n_inner_used: Tuple[int, ...]
     iters_done: int
-    trace: Optional[list] = None
+    trace: Optional[list] = None          # packed: level_iters[l] + 1 rows per level
+    level_iters: Tuple[int, ...] = ()     # outer iterations made per level
+    change: Tuple[float, ...] = ()        # last relative change per level (tol > 0)
 
 
-def _report(rep, n_levels, trace_buf, n_rows):
+def _report(rep, n_levels, trace_buf):
+    made = tuple(rep.level_iters[:n_levels])
     tr = None
     if trace_buf is not None:
+        n_rows = sum(m + 1 for m in made)
         tr = [tuple(trace_buf[4 * i:4 * i + 4]) for i in range(n_rows)]
     return FbsReport(rep.E, rep.E_eps, rep.E1, rep.E2, tuple(rep.beta_used[:n_levels]),
-                     tuple(rep.n_inner_used[:n_levels]), rep.iters_done, tr)
+                     tuple(rep.n_inner_used[:n_levels]), rep.iters_done, tr, made,
+                     tuple(rep.change[:n_levels]))
 
 
 def fbs_solve(plan: Plan, Y, params: FbsParams, f0=None):
@@ -328,7 +339,7 @@ def fbs_solve(plan: Plan, Y, params: FbsParams, f0=None):
     with torch.cuda.device(Y.device):
         check(_native.lib().cbct_fbs_solve(plan.handle, _ptr(Y), _ptr(f), ctypes.byref(p),
                                            ctypes.byref(rep), _stream_of(Y)), "cbct_fbs_solve")
-    return f, _report(rep, len(params.iters), buf, n_rows)
+    return f, _report(rep, len(params.iters), buf)
 
 
 class FbsState:
@@ -368,7 +379,7 @@ class FbsState:
     def report(self) -> FbsReport:
         rep = cbct_fbs_report()
         check(self._lib.cbct_fbs_report_get(self._h, ctypes.byref(rep)), "cbct_fbs_report_get")
-        return _report(rep, len(self.params.iters), None, 0)
+        return _report(rep, len(self.params.iters), None)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

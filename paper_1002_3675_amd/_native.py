@@ -25,21 +25,29 @@ class cbct_geom(ctypes.Structure):
                 ("au", ctypes.c_double), ("av", ctypes.c_double),
                 ("sad", ctypes.c_double), ("sdd", ctypes.c_double),
                 ("n_views", ctypes.c_int32), ("angles", ctypes.POINTER(ctypes.c_double)),
-                ("step", ctypes.c_double), ("u_off", ctypes.c_double), ("v_off", ctypes.c_double)]
+                ("step", ctypes.c_double), ("u_off", ctypes.c_double), ("v_off", ctypes.c_double),
+                ("x_off", ctypes.c_double), ("y_off", ctypes.c_double), ("z_off", ctypes.c_double)]
+
+
+MAX_LEVELS = 4  # CBCT_MAX_LEVELS
 
 
 class cbct_fbs_params(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_double), ("n_levels", ctypes.c_int32),
-                ("iters", ctypes.c_int32 * 2), ("beta", ctypes.c_double * 2),
-                ("eps", ctypes.c_double), ("n_inner", ctypes.c_int32 * 2),
-                ("trace_energy", ctypes.c_int32), ("gradient", ctypes.c_int32)]
+                ("iters", ctypes.c_int32 * MAX_LEVELS), ("beta", ctypes.c_double * MAX_LEVELS),
+                ("eps", ctypes.c_double), ("n_inner", ctypes.c_int32 * MAX_LEVELS),
+                ("trace_energy", ctypes.c_int32), ("gradient", ctypes.c_int32),
+                ("tol", ctypes.c_double)]
 
 
 class cbct_fbs_report(ctypes.Structure):
     _fields_ = [("E", ctypes.c_double), ("E_eps", ctypes.c_double),
                 ("E1", ctypes.c_double), ("E2", ctypes.c_double),
-                ("beta_used", ctypes.c_double * 2), ("n_inner_used", ctypes.c_int32 * 2),
-                ("iters_done", ctypes.c_int32), ("trace", ctypes.POINTER(ctypes.c_double))]
+                ("beta_used", ctypes.c_double * MAX_LEVELS),
+                ("n_inner_used", ctypes.c_int32 * MAX_LEVELS),
+                ("level_iters", ctypes.c_int32 * MAX_LEVELS), ("iters_done", ctypes.c_int32),
+                ("change", ctypes.c_double * MAX_LEVELS),
+                ("trace", ctypes.POINTER(ctypes.c_double))]
 
 
 # name -> (restype, argtypes); every symbol declared in include/cbct.h

@@ -79,9 +79,9 @@ GridConst grid_of(const cbct_geom &g) {
     c.hx = (float)g.hx;
     c.hy = (float)g.hy;
     c.hz = (float)g.hz;
-    c.x0 = (float)(-0.5 * (g.nx - 1) * g.hx);
-    c.y0 = (float)(-0.5 * (g.ny - 1) * g.hy);
-    c.z0 = (float)(-0.5 * (g.nz - 1) * g.hz);
+    c.x0 = (float)(-0.5 * (g.nx - 1) * g.hx + g.x_off);
+    c.y0 = (float)(-0.5 * (g.ny - 1) * g.hy + g.y_off);
+    c.z0 = (float)(-0.5 * (g.nz - 1) * g.hz + g.z_off);
     return c;
 }
 
@@ -221,7 +221,13 @@ int validate_geom(const cbct_geom *g) {
         return set_error(CBCT_EINVAL, "spacings must be positive");
     if (!(g->sad > 0) || !(g->sdd > g->sad))
         return set_error(CBCT_EINVAL, "need sdd > sad > 0");
-    const double hx = 0.5 * (g->nx + 1) * g->hx, hy = 0.5 * (g->ny + 1) * g->hy;
+    if (!isfinite(g->u_off) || !isfinite(g->v_off))
+        return set_error(CBCT_EINVAL, "non-finite detector offset");
+    if (!isfinite(g->x_off) || !isfinite(g->y_off) || !isfinite(g->z_off))
+        return set_error(CBCT_EINVAL, "non-finite volume offset");
+    // every corner of the zero-bordered grid stays inside the source orbit
+    const double hx = 0.5 * (g->nx + 1) * g->hx + fabs(g->x_off);
+    const double hy = 0.5 * (g->ny + 1) * g->hy + fabs(g->y_off);
     if (!(g->sad > sqrt(hx * hx + hy * hy)))
         return set_error(CBCT_EINVAL, "source orbit must lie outside the grid");
     const double padded = (double)(g->nx + 2) * (g->ny + 2) * (g->nz + 2);
@@ -237,8 +243,6 @@ int validate_geom(const cbct_geom *g) {
         return set_error(CBCT_EINVAL, "grid dimension above 32000");
     if (std::ceil(g->nu / 32.0) * std::ceil(g->nv / 8.0) * g->n_views > 2147483647.0)
         return set_error(CBCT_EINVAL, "too many detector tiles");
-    if (!isfinite(g->u_off) || !isfinite(g->v_off))
-        return set_error(CBCT_EINVAL, "non-finite detector offset");
     if (g->angles)
         for (int k = 0; k < g->n_views; ++k)
             if (!isfinite(g->angles[k])) return set_error(CBCT_EINVAL, "non-finite angle");
@@ -268,11 +272,16 @@ extern "C" int cbct_plan_create(const cbct_geom *gin, cbct_plan **out) {
         std::unique_ptr<cbct_plan> p(new cbct_plan());
         p->g = *gin;
         if (!(p->g.step > 0)) p->g.step = 0.5 * std::min(gin->hx, std::min(gin->hy, gin->hz));
-        // sample indices n = t / step reach (sdd + half the grid) / step
-        // (the detector lies beyond every voxel); keep them well inside the
-        // 16-bit segment numbers of the transpose (n < 32767 * 256)
-        if ((p->g.sdd + 0.5 * sqrt(pow(p->g.nx * p->g.hx, 2) + pow(p->g.ny * p->g.hy, 2) +
-                                   pow(p->g.nz * p->g.hz, 2))) / p->g.step > 8.0e6)
+        // sample indices n = t / step stay below (the source's distance to
+        // the grid centre + half the grid diagonal) / step; keep them well
+        // inside the 16-bit segment numbers of the transpose
+        // (n < 32767 * 256)
+        const double reach =
+            std::max(p->g.sdd, p->g.sad + sqrt(pow(p->g.x_off, 2) + pow(p->g.y_off, 2) +
+                                               pow(p->g.z_off, 2))) +
+            0.5 * sqrt(pow((p->g.nx + 1) * p->g.hx, 2) + pow((p->g.ny + 1) * p->g.hy, 2) +
+                       pow((p->g.nz + 1) * p->g.hz, 2));
+        if (reach / p->g.step > 8.0e6)
             return set_error(CBCT_EINVAL, "step too small for the source distance");
         p->angles.resize(gin->n_views);
         for (int k = 0; k < gin->n_views; ++k)
@@ -283,7 +292,8 @@ extern "C" int cbct_plan_create(const cbct_geom *gin, cbct_plan **out) {
         const double h[3] = {g.hx, g.hy, g.hz};
         const int n[3] = {g.nx, g.ny, g.nz};
         double x0[3];
-        for (int a = 0; a < 3; ++a) x0[a] = -0.5 * (n[a] - 1) * h[a];
+        const double off[3] = {g.x_off, g.y_off, g.z_off};
+        for (int a = 0; a < 3; ++a) x0[a] = -0.5 * (n[a] - 1) * h[a] + off[a];
         p->h_views.resize(g.n_views);
         for (int k = 0; k < g.n_views; ++k) {
             const double th = p->angles[k], cs = cos(th), sn = sin(th);
@@ -632,15 +642,19 @@ struct Level {
     const float *Y = nullptr;
     float *f = nullptr;
     float *g = nullptr, *z = nullptr, *r = nullptr, *pad = nullptr, *cells = nullptr;
+    float *fprev = nullptr;  // f before the outer iteration (tol > 0)
     double beta = 0, tau = 0, prox_step = 0;
     int n_inner = 0, iters = 0;
+    int made = 0;            // outer iterations made
+    double change = 0;       // relative change of the last one (tol > 0)
+    bool stopped = false;    // the tolerance was met
     size_t nvox = 0, nmeas = 0;
 };
 
 }  // namespace
 
 struct cbct_fbs_state {
-    Level lv[2];
+    Level lv[CBCT_MAX_LEVELS];
     int n_levels = 1;
     int level = 0, iter = 0;
     bool done = false;
@@ -656,8 +670,16 @@ struct cbct_fbs_state {
 
 namespace {
 
+// The next coarser level: a coarse cell averages fine voxels (2i, 2i + 1)
+// along each axis and sits at their centre, so an odd axis moves the
+// coarse grid's centre half a fine spacing down; pixels likewise.
 cbct_geom coarse_geom(const cbct_geom &g) {
     cbct_geom c = g;
+    c.x_off = g.x_off - 0.5 * g.hx * (double)(g.nx & 1);
+    c.y_off = g.y_off - 0.5 * g.hy * (double)(g.ny & 1);
+    c.z_off = g.z_off - 0.5 * g.hz * (double)(g.nz & 1);
+    c.u_off = g.u_off - 0.5 * g.au * (double)(g.nu & 1);
+    c.v_off = g.v_off - 0.5 * g.av * (double)(g.nv & 1);
     c.nx = g.nx / 2;
     c.ny = g.ny / 2;
     c.nz = g.nz / 2;
@@ -674,15 +696,21 @@ cbct_geom coarse_geom(const cbct_geom &g) {
 
 int validate_params(const cbct_geom &g, const cbct_fbs_params *prm) {
     if (!prm) return set_error(CBCT_EINVAL, "params NULL");
-    if (prm->n_levels < 1 || prm->n_levels > 2) return set_error(CBCT_EINVAL, "n_levels must be 1 or 2");
+    if (prm->n_levels < 1 || prm->n_levels > CBCT_MAX_LEVELS)
+        return set_error(CBCT_EINVAL, "n_levels must be 1 to CBCT_MAX_LEVELS");
     if (!(prm->mu > 0) || !isfinite(prm->mu)) return set_error(CBCT_EINVAL, "mu must be > 0");
     if (!(prm->eps > 0) || !isfinite(prm->eps)) return set_error(CBCT_EINVAL, "eps must be > 0");
     for (int l = 0; l < prm->n_levels; ++l) {
         if (prm->iters[l] < 0) return set_error(CBCT_EINVAL, "iters must be >= 0");
         if (!isfinite(prm->beta[l])) return set_error(CBCT_EINVAL, "beta not finite");
     }
-    if (prm->n_levels == 2 && ((g.nx | g.ny | g.nz | g.nu | g.nv) & 1))
-        return set_error(CBCT_EINVAL, "two levels need even nx, ny, nz, nu, nv");
+    if (!(prm->tol >= 0) || !isfinite(prm->tol)) return set_error(CBCT_EINVAL, "tol must be >= 0");
+    cbct_geom c = g;
+    for (int l = 1; l < prm->n_levels; ++l) {
+        if (c.nx < 2 || c.ny < 2 || c.nz < 2 || c.nu < 2 || c.nv < 2)
+            return set_error(CBCT_EINVAL, "a coarser level would have a size below 1");
+        c = coarse_geom(c);
+    }
     if (prm->gradient != 0 && prm->gradient != 1)
         return set_error(CBCT_EINVAL, "gradient must be 0 (transpose) or 1 (Eq. (2))");
     return CBCT_OK;
@@ -690,10 +718,11 @@ int validate_params(const cbct_geom &g, const cbct_fbs_params *prm) {
 
 // Device bytes of one level's state; the Eq. (2) gradient needs no
 // transpose workspace.
-size_t level_bytes(const cbct_geom &g, bool own_yf, int gradient) {
+size_t level_bytes(const cbct_geom &g, bool own_yf, int gradient, bool tol) {
     const size_t nvox = nvox_of(g), nmeas = nmeas_of(g);
     size_t b = sizeof(float) * (2 * nvox + nmeas + padded_of(g));
     if (gradient == 0) b += bp_workspace_bytes(g, sizeof(float));
+    if (tol) b += sizeof(float) * nvox;
     if (own_yf) b += sizeof(float) * (nvox + nmeas);
     return b;
 }
@@ -762,17 +791,40 @@ int fbs_iteration(cbct_fbs_state *st, Level &L, hipStream_t s, bool have_residua
     return rc;
 }
 
+// Relative change ||f - fprev|| / ||f|| of the outer iteration just made
+// (0 when both are zero, +inf when only f is); syncs the stream.
+int level_change(cbct_fbs_state *st, Level &L, hipStream_t s, double *out) {
+    int np = 0;
+    int rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_diff_sums(L.f, L.fprev, L.nvox, st->partials, &np, s); }),
+                       "change sums");
+    if (!rc)
+        rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_reduce_sum(st->partials, np, st->dsc, 2, s); }),
+                       "reduce");
+    double h[2] = {0, 0};
+    if (!rc) rc = check_hip(hipMemcpyAsync(h, st->dsc, sizeof(h), hipMemcpyDeviceToHost, s), "readback");
+    if (!rc) rc = check_hip(hipStreamSynchronize(s), "sync");
+    if (rc) return rc;
+    *out = h[1] > 0 ? sqrt(h[0] / h[1]) : (h[0] > 0 ? INFINITY : 0.0);
+    return CBCT_OK;
+}
+
 }  // namespace
 
 extern "C" size_t cbct_fbs_footprint(const cbct_geom *g, const cbct_fbs_params *prm) {
     if (validate_geom(g) || validate_params(*g, prm)) return 0;
     size_t b = sizeof(float) * (nvox_of(*g) + nmeas_of(*g));  // caller's f and Y
-    b += level_bytes(*g, false, prm->gradient);
-    if (prm->n_levels == 2) b += level_bytes(coarse_geom(*g), true, prm->gradient);
+    const bool tol = prm->tol > 0;
+    b += level_bytes(*g, false, prm->gradient, tol);
+    cbct_geom c = *g;
+    for (int l = 1; l < prm->n_levels; ++l) {
+        c = coarse_geom(c);
+        b += level_bytes(c, true, prm->gradient, tol);
+    }
     // partials and scalars
     dim3 pg((g->nu + 31) / 32, (g->nv + 7) / 8, g->n_views);  // projector tile grid
     size_t np = std::max((size_t)pg.x * pg.y * pg.z,
                          (size_t)2 * ((g->nx + 63) / 64) * ((g->ny + 3) / 4) * g->nz);
+    if (tol) np = std::max(np, (size_t)2 * DIFF_BLOCKS);
     b += sizeof(double) * (np + 8);
     return b;
 }
@@ -792,19 +844,22 @@ extern "C" int cbct_fbs_init(const cbct_plan *fine, const float *Y, float *f,
         st->lv[fi].plan = fine;
         st->lv[fi].Y = Y;
         st->lv[fi].f = f;
-        if (prm->n_levels == 2) {
-            std::lock_guard<std::mutex> lk(fine->coarse_mu);
-            if (!fine->coarse) {
-                cbct_geom cg = coarse_geom(fine->g);
-                cg.angles = fine->angles.data();
+        // the chain of coarser plans, each cached in the next finer one
+        for (int l = fi - 1; l >= 0; --l) {
+            const cbct_plan *up = st->lv[l + 1].plan;
+            std::lock_guard<std::mutex> lk(up->coarse_mu);
+            if (!up->coarse) {
+                cbct_geom cg = coarse_geom(up->g);
+                cg.angles = up->angles.data();
                 cbct_plan *cp = nullptr;
                 rc = cbct_plan_create(&cg, &cp);
                 if (rc) return rc;
-                fine->coarse = cp;
+                up->coarse = cp;
             }
-            st->lv[0].plan = fine->coarse;
+            st->lv[l].plan = up->coarse;
         }
-        size_t np = 8;
+        const bool tol = prm->tol > 0;
+        size_t np = tol ? (size_t)2 * DIFF_BLOCKS : 8;
         for (int l = 0; l < st->n_levels; ++l) {
             Level &L = st->lv[l];
             const cbct_geom &g = L.plan->g;
@@ -829,17 +884,21 @@ extern "C" int cbct_fbs_init(const cbct_plan *fine, const float *Y, float *f,
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.z, sizeof(float) * L.nvox, s);
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.r, sizeof(float) * L.nmeas, s);
             if (!rc) rc = alloc_owned(st.get(), (void **)&L.pad, sizeof(float) * padded_count(p), s);
+            if (!rc && tol) rc = alloc_owned(st.get(), (void **)&L.fprev, sizeof(float) * L.nvox, s);
             if (!rc && prm->gradient == 0) {
                 rc = alloc_owned(st.get(), (void **)&L.cells, bp_workspace_bytes(p.g, sizeof(float)), s);
                 if (!rc) rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_bp_prepare(p, L.cells, sizeof(float), s); }), "ray table");
             }
         }
-        if (!rc && st->n_levels == 2) {
-            const cbct_geom &g = fine->g;
-            rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_bin_detector(Y, g.nu, g.nv, g.n_views, (float *)st->lv[0].Y, s); }),
+        // data and start of each coarser level from the next finer one
+        for (int l = fi - 1; !rc && l >= 0; --l) {
+            const Level &U = st->lv[l + 1];
+            Level &L = st->lv[l];
+            const cbct_geom &g = U.plan->g;
+            rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_bin_detector(U.Y, g.nu, g.nv, g.n_views, (float *)L.Y, s); }),
                            "bin detector");
             if (!rc)
-                rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_restrict(f, g.nx, g.ny, g.nz, st->lv[0].f, s); }), "restrict");
+                rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_restrict(U.f, g.nx, g.ny, g.nz, L.f, s); }), "restrict");
         }
         // beta, tau, inner count per level
         for (int l = 0; !rc && l < st->n_levels; ++l) {
@@ -887,7 +946,7 @@ extern "C" int cbct_fbs_step(cbct_fbs_state *st, int32_t n_iters, void *stream) 
         int left = n_iters;
         while (!st->done && !rc) {
             Level &L = st->lv[st->level];
-            if (st->iter < L.iters) {
+            if (st->iter < L.iters && !L.stopped) {
                 if (left == 0) break;
                 const bool tr = st->prm.trace_energy != 0;
                 if (tr) {
@@ -896,9 +955,19 @@ extern "C" int cbct_fbs_step(cbct_fbs_state *st, int32_t n_iters, void *stream) 
                     if (rc) break;
                     st->trace.insert(st->trace.end(), row, row + 4);
                 }
-                rc = fbs_iteration(st, L, s, tr);
+                if (L.fprev)
+                    rc = check_hip(hipMemcpyAsync(L.fprev, L.f, sizeof(float) * L.nvox,
+                                                  hipMemcpyDeviceToDevice, s),
+                                   "keep f");
+                if (!rc) rc = fbs_iteration(st, L, s, tr);
+                if (rc) break;
                 ++st->iter;
+                L.made = st->iter;
                 --left;
+                if (L.fprev) {
+                    rc = level_change(st, L, s, &L.change);
+                    if (!rc && L.change <= st->prm.tol) L.stopped = true;
+                }
                 continue;
             }
             // level finished
@@ -941,12 +1010,14 @@ extern "C" int cbct_fbs_report_get(const cbct_fbs_state *st, cbct_fbs_report *re
     rep->E1 = st->have_final ? st->final_e[2] : 0.0;
     rep->E2 = st->have_final ? st->final_e[3] : 0.0;
     int done = 0;
-    for (int l = 0; l < 2; ++l) {
-        rep->beta_used[l] = l < st->n_levels ? st->lv[l].beta : 0.0;
-        rep->n_inner_used[l] = l < st->n_levels ? st->lv[l].n_inner : 0;
-        if (l < st->level) done += st->lv[l].iters;
+    for (int l = 0; l < CBCT_MAX_LEVELS; ++l) {
+        const bool in = l < st->n_levels;
+        rep->beta_used[l] = in ? st->lv[l].beta : 0.0;
+        rep->n_inner_used[l] = in ? st->lv[l].n_inner : 0;
+        rep->level_iters[l] = in ? st->lv[l].made : 0;
+        rep->change[l] = in ? st->lv[l].change : 0.0;
+        done += rep->level_iters[l];
     }
-    done += st->done ? st->lv[st->n_levels - 1].iters : st->iter;
     rep->iters_done = done;
     if (rep->trace && !st->trace.empty())
         memcpy(rep->trace, st->trace.data(), sizeof(double) * st->trace.size());

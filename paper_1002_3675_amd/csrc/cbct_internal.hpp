@@ -72,7 +72,7 @@ struct cbct_plan {
     int device = 0;
     mutable std::mutex lam_mu;
     mutable std::vector<std::pair<int, double>> lam_cache;
-    // coarse level of the two-level schedule, created on first use
+    // next coarser multigrid level, created on first use
     mutable std::mutex coarse_mu;
     mutable cbct_plan *coarse = nullptr;
 };
@@ -123,6 +123,11 @@ hipError_t launch_reduce_sum(const double *partials, int n, double *out, int n_o
                              hipStream_t s);
 size_t tv_energy_partials_count(const GridConst &gc);
 
+// Per-block partial sums (sum (a - b)^2, sum a^2), two doubles per block,
+// at most DIFF_BLOCKS blocks: the relative change of an outer iteration.
+constexpr int DIFF_BLOCKS = 1024;
+hipError_t launch_diff_sums(const float *a, const float *b, size_t n, double *partials,
+                            int *n_partials, hipStream_t s);
 hipError_t launch_sumsq(const float *x, size_t n, double *partials, int *n_partials,
                         hipStream_t s);
 hipError_t launch_fill(float *x, size_t n, float v, hipStream_t s);

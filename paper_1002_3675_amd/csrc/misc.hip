@@ -1,4 +1,4 @@
-// Small kernels of the solver: reductions, fills, and the two-level
+// Small kernels of the solver: reductions, fills, and the multigrid
 // transfers (2x2 detector binning, 2x2x2 restriction, trilinear
 // prolongation at cell-centred fine voxels).
 #include "cbct_internal.hpp"
@@ -20,6 +20,33 @@ __global__ __launch_bounds__(256) void k_sumsq(const float *__restrict__ x, long
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Partial sums of (a - b)^2 and a^2 per block, in double, fixed order.
+__global__ __launch_bounds__(256) void k_diff_sums(const float *__restrict__ a,
+                                                   const float *__restrict__ b, long long n,
+                                                   double *__restrict__ partials) {
+    double d = 0.0, m = 0.0;
+    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < n;
+         t += (long long)gridDim.x * 256) {
+        const double x = a[t], e = x - (double)b[t];
+        d += e * e;
+        m += x * x;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        d += __shfl_down(d, off, 64);
+        m += __shfl_down(m, off, 64);
+    }
+    __shared__ double red[2][4];
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = d;
+        red[1][threadIdx.x >> 6] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        partials[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
 }
 
 // out[c] = sum_i partials[i * ncols + c], one block, fixed order per lane.
@@ -138,6 +165,15 @@ hipError_t launch_sumsq(const float *x, size_t n, double *partials, int *n_parti
     if (b > 4096) b = 4096;
     hipLaunchKernelGGL(k_sumsq, dim3(b), dim3(256), 0, s, x, (long long)n, partials);
     *n_partials = (int)b;
+    return hipGetLastError();
+}
+
+hipError_t launch_diff_sums(const float *a, const float *b, size_t n, double *partials,
+                            int *n_partials, hipStream_t s) {
+    unsigned nb = grid_for((long long)n);
+    if (nb > (unsigned)DIFF_BLOCKS) nb = DIFF_BLOCKS;
+    hipLaunchKernelGGL(k_diff_sums, dim3(nb), dim3(256), 0, s, a, b, (long long)n, partials);
+    *n_partials = (int)nb;
     return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@ declares, and the ctypes mirrors of its structs have the C layout
 (no compute calls: these run without a GPU)."""
 
 import ctypes
+import dataclasses
 import os
 import re
 import subprocess
@@ -49,13 +50,17 @@ def test_struct_layout_matches_c():
 int main(void) {
   printf("cbct_geom %zu\n", sizeof(cbct_geom));
   P(cbct_geom, hx) P(cbct_geom, nu) P(cbct_geom, au) P(cbct_geom, n_views)
-  P(cbct_geom, angles) P(cbct_geom, step)
+  P(cbct_geom, angles) P(cbct_geom, step) P(cbct_geom, u_off) P(cbct_geom, v_off)
+  P(cbct_geom, x_off) P(cbct_geom, y_off) P(cbct_geom, z_off)
+  printf("MAX_LEVELS.value %d\n", CBCT_MAX_LEVELS);
   printf("cbct_fbs_params %zu\n", sizeof(cbct_fbs_params));
   P(cbct_fbs_params, iters) P(cbct_fbs_params, beta) P(cbct_fbs_params, eps)
   P(cbct_fbs_params, n_inner) P(cbct_fbs_params, trace_energy)
+  P(cbct_fbs_params, gradient) P(cbct_fbs_params, tol)
   printf("cbct_fbs_report %zu\n", sizeof(cbct_fbs_report));
   P(cbct_fbs_report, beta_used) P(cbct_fbs_report, n_inner_used)
-  P(cbct_fbs_report, iters_done) P(cbct_fbs_report, trace)
+  P(cbct_fbs_report, level_iters) P(cbct_fbs_report, iters_done)
+  P(cbct_fbs_report, change) P(cbct_fbs_report, trace)
   return 0;
 }
 """
@@ -72,6 +77,7 @@ int main(void) {
             want[k] = int(v)
     S = {"cbct_geom": _native.cbct_geom, "cbct_fbs_params": _native.cbct_fbs_params,
          "cbct_fbs_report": _native.cbct_fbs_report}
+    assert want.pop("MAX_LEVELS.value") == _native.MAX_LEVELS
     for k, v in want.items():
         if "." in k:
             s, f = k.split(".")
@@ -120,3 +126,25 @@ def test_footprint_is_host_arithmetic():
     # at least Y, f, g, z, r and the cell workspace of the fine level
     assert one >= 4 * (3 * nvox + 2 * nmeas + 8 * 513 * 513 * 71)
     assert two > one
+
+
+def test_solver_parameters_are_checked_on_the_host():
+    """Levels, tolerance and shifts are validated before any device call:
+    footprint() returns 0 for what init would refuse."""
+    import paper_1002_3675_amd as cb
+    from workloads import Geometry, head_geometry
+    g = head_geometry(40)
+    assert cb.footprint(g, cb.FbsParams(iters=(5, 5, 5, 5))) > \
+        cb.footprint(g, cb.FbsParams(iters=(5, 5, 5))) > cb.footprint(g, cb.FbsParams(iters=(5, 5)))
+    assert cb.footprint(g, cb.FbsParams(iters=(5, 5), tol=1e-3)) > \
+        cb.footprint(g, cb.FbsParams(iters=(5, 5)))
+    with pytest.raises(ValueError):
+        cb.FbsParams(iters=(1, 1, 1, 1, 1)).to_c()
+    assert cb.footprint(g, cb.FbsParams(iters=(5, 5), tol=-1.0)) == 0
+    assert cb.footprint(g, cb.FbsParams(iters=(5, 5), tol=float("nan"))) == 0
+    small = Geometry(6, 6, 3, 4.0, 4.0, 4.0, 16, 12, 3.2, 3.2, 1000.0, 1500.0, 4)
+    assert cb.footprint(small, cb.FbsParams(iters=(1, 1))) > 0    # 3 -> 1 plane
+    assert cb.footprint(small, cb.FbsParams(iters=(1, 1, 1))) == 0  # 1 -> 0 planes
+    # a shifted grid must still lie inside the source orbit
+    assert cb.footprint(dataclasses.replace(g, x_off=900.0), cb.FbsParams(iters=(5,))) == 0
+    assert cb.footprint(dataclasses.replace(g, z_off=float("inf")), cb.FbsParams(iters=(5,))) == 0
