@@ -127,6 +127,8 @@ def parse():
                          "mean one-at-a-time service time")
     ap.add_argument("--lowdose", action="store_true",
                     help="also run the 12-point low-dose quality sweep")
+    ap.add_argument("--skip-schedules", action="store_true",
+                    help="leave out the multigrid schedule comparison (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (the reference "
                          "dispatch that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -498,7 +500,7 @@ def main():
     ms_pt = time_op(torch, lambda: plan.backproject(yr, out=fb), args.ops_reps)
     eq2 = eq2_comparison(torch, cb, plan, Y, params, f, rep, yr, fb, ms_pt, args.ops_reps)
     del fr, yr, yb, fb
-    schedules = multigrid_schedules(torch, cb, plan, case, Y)
+    schedules = None if args.skip_schedules else multigrid_schedules(torch, cb, plan, case, Y)
 
     out = {
         "metric": METRIC,
