@@ -710,6 +710,9 @@ int validate_params(const cbct_geom &g, const cbct_fbs_params *prm) {
         if (c.nx < 2 || c.ny < 2 || c.nz < 2 || c.nu < 2 || c.nv < 2)
             return set_error(CBCT_EINVAL, "a coarser level would have a size below 1");
         c = coarse_geom(c);
+        // the coarser plan must be creatable too (its padded grid is larger)
+        const int rc = validate_geom(&c);
+        if (rc) return rc;
     }
     if (prm->gradient != 0 && prm->gradient != 1)
         return set_error(CBCT_EINVAL, "gradient must be 0 (transpose) or 1 (Eq. (2))");

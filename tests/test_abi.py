@@ -145,6 +145,11 @@ def test_solver_parameters_are_checked_on_the_host():
     small = Geometry(6, 6, 3, 4.0, 4.0, 4.0, 16, 12, 3.2, 3.2, 1000.0, 1500.0, 4)
     assert cb.footprint(small, cb.FbsParams(iters=(1, 1))) > 0    # 3 -> 1 plane
     assert cb.footprint(small, cb.FbsParams(iters=(1, 1, 1))) == 0  # 1 -> 0 planes
+    # a coarser level's zero-bordered grid is wider: it too must lie inside
+    # the source orbit (half diagonal 71.4 mm at the fine level, 72.1 coarse)
+    tight = Geometry(100, 100, 8, 1.0, 1.0, 1.0, 64, 16, 2.0, 2.0, 72.0, 150.0, 4)
+    assert cb.footprint(tight, cb.FbsParams(iters=(1,))) > 0
+    assert cb.footprint(tight, cb.FbsParams(iters=(1, 1))) == 0
     # a shifted grid must still lie inside the source orbit
     assert cb.footprint(dataclasses.replace(g, x_off=900.0), cb.FbsParams(iters=(5,))) == 0
     assert cb.footprint(dataclasses.replace(g, z_off=float("inf")), cb.FbsParams(iters=(5,))) == 0
