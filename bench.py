@@ -32,8 +32,9 @@ METRIC = ("GRay-samples/s for P and P^T (%HBM peak); recon s/volume; "
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 PEAK_ALU_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, non-packed
 # algorithmic floating-point operations per ray sample of the projector and
-# of the transpose's cell pass (coordinate FMAs, floors, fractions, the
-# trilinear weights and the accumulation; counted in the design doc)
+# of the transpose's cell pass: the coordinate (3 FMA = 6), floors (3),
+# fractions (3), and the 8 trilinear corner weights times the residual with
+# their accumulation (22)
 FLOPS_PER_SAMPLE = 34.0
 TV_BYTES_PER_VOXEL = 12.0   # per sweep: read z and g, write z
 
@@ -395,7 +396,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the reconstruction path runs on a single "
-              "MI355X (multi-GPU sharding by views is described in DESIGN.md, not built); "
+              "MI355X (sharding a solve by views over several GPUs is designed, not built); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
