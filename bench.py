@@ -235,15 +235,20 @@ def serving_benchmark(torch, cb, n_req, seed=5000, load=0.8):
     params = cb.FbsParams(mu=1e-3, iters=(20, 20), eps=1e-3)
     # one-at-a-time service times (the first solve of a geometry also pays
     # its beta setup; warm every plan first so both runs see cached beta)
-    for _, g, Y in reqs:
+    for q, (_, g, Y) in enumerate(reqs):
         cb.fbs_solve(ex.plan_for(g), Y, params)
+        if (q + 1) % 25 == 0:
+            torch.cuda.synchronize()
+            log("serving: %d of %d requests warmed" % (q + 1, n_req))
     torch.cuda.synchronize()
     serial = []
-    for _, g, Y in reqs:
+    for q, (_, g, Y) in enumerate(reqs):
         t0 = time.perf_counter()
         cb.fbs_solve(ex.plan_for(g), Y, params)
         torch.cuda.synchronize()
         serial.append(time.perf_counter() - t0)
+        if (q + 1) % 25 == 0:
+            log("serving: %d of %d requests timed alone" % (q + 1, n_req))
     log("serving: %d requests made and timed alone in %.1f s" % (n_req, time.perf_counter() - t))
     mean_s = float(np.mean(serial))
     rate = load / mean_s
@@ -269,6 +274,8 @@ def serving_benchmark(torch, cb, n_req, seed=5000, load=0.8):
             if delay > 0:
                 time.sleep(delay)
             futs.append(srv.submit(Request(g, Y, params, arrival=time.perf_counter())))
+            if len(futs) % 25 == 0:
+                log("serving: %d of %d requests submitted" % (len(futs), n_req))
 
     th = threading.Thread(target=feed)
     th.start()
