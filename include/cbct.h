@@ -6,7 +6,7 @@
  * undersampled and noisy projection data via total variation"), where E1 is
  * the TV semi-norm (voxel mean of |grad f|) and E2 the mean squared
  * residual of the cone-beam projections, by the forward-backward splitting
- * of Algorithm A1 with a two-level coarse-to-fine schedule.
+ * of Algorithm A1 with a cascadic coarse-to-fine multigrid schedule.
  *
  * Units: lengths in mm, attenuation f in 1/mm, projections Y dimensionless
  * (line integrals).
@@ -16,8 +16,9 @@
  *     (angles[k], or 2*pi*k/n_views when angles is NULL): source at
  *     R(theta)(0, -sad, 0); detector centre at R(theta)(0, sdd - sad, 0);
  *     detector u axis R(theta)(1, 0, 0), v axis z.
- *   - Pixel (i, j) centre: u = (i - (nu-1)/2) au, v = (j - (nv-1)/2) av.
- *   - Voxel (i, j, k) centre: x = (i - (nx-1)/2) hx, likewise y, z.
+ *   - Pixel (i, j) centre: u = (i - (nu-1)/2) au + u_off,
+ *     v = (j - (nv-1)/2) av + v_off.
+ *   - Voxel (i, j, k) centre: x = (i - (nx-1)/2) hx + x_off, likewise y, z.
  *   - Volumes are float32 [nz][ny][nx] (x fastest); projection stacks are
  *     float32 [n_views][nv][nu] (u fastest).
  *   - Array arguments are DEVICE pointers owned by the caller; the library

@@ -1,6 +1,6 @@
 // C ABI of the cone-beam library: plans, operators, and the forward-backward
-// splitting solver of Algorithm A1 with the two-level coarse-to-fine
-// schedule.
+// splitting solver of Algorithm A1 with the cascadic coarse-to-fine
+// multigrid schedule (up to CBCT_MAX_LEVELS levels).
 #include <math.h>
 #include <string.h>
 
