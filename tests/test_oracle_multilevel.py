@@ -137,3 +137,34 @@ def test_monotone_energy_three_levels(odd_case):
         row += n + 1
     with pytest.raises(ValueError):
         oracle.fbs_solve(g, Y, 1e-3, (1, 1, 1, 1, 1))
+
+
+try:
+    from hypothesis import given, settings, strategies as st
+
+    @settings(max_examples=25, deadline=None)
+    @given(st.integers(2, 11), st.integers(2, 11), st.integers(2, 11),
+           st.integers(2, 13), st.integers(2, 13),
+           st.floats(-20.0, 20.0), st.floats(-20.0, 20.0), st.floats(-20.0, 20.0),
+           st.floats(-9.0, 9.0), st.floats(-9.0, 9.0))
+    def test_coarse_centres_random_sizes_and_shifts(nx, ny, nz, nu, nv, xo, yo, zo, uo, vo):
+        """Any sizes (odd or even) and shifts: the 2x2x2 and 2x2 means of a
+        linear field sit exactly at the coarse centres; the shifts, the
+        dimensions and the pitches of the coarse level follow."""
+        g = Geometry(nx, ny, nz, 1.5, 2.0, 2.5, nu, nv, 1.2, 1.4, 500.0, 800.0, 1,
+                     u_off=uo, v_off=vo, x_off=xo, y_off=yo, z_off=zo)
+        c = oracle.coarse_geometry(g)
+        a = (0.013, -0.021, 0.007)
+        z, y, x = np.meshgrid(_centres(nz, g.hz, zo), _centres(ny, g.hy, yo),
+                              _centres(nx, g.hx, xo), indexing="ij")
+        zc, yc, xc = np.meshgrid(_centres(c.nz, c.hz, c.z_off), _centres(c.ny, c.hy, c.y_off),
+                                 _centres(c.nx, c.hx, c.x_off), indexing="ij")
+        got = oracle.restrict(a[0] * x + a[1] * y + a[2] * z)
+        assert np.max(np.abs(got - (a[0] * xc + a[1] * yc + a[2] * zc))) <= 1e-12
+        v, u = np.meshgrid(_centres(nv, g.av, vo), _centres(nu, g.au, uo), indexing="ij")
+        vc, uc = np.meshgrid(_centres(c.nv, c.av, c.v_off), _centres(c.nu, c.au, c.u_off),
+                             indexing="ij")
+        got = oracle.bin_detector((a[0] * u + a[1] * v)[None])
+        assert np.max(np.abs(got[0] - (a[0] * uc + a[1] * vc))) <= 1e-12
+except ImportError:  # pragma: no cover
+    pass
