@@ -118,7 +118,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-views", type=int, default=4,
+    ap.add_argument("--cpu-views", type=int, default=16,
                     help="views of the head scan the CPU oracle sample uses")
     ap.add_argument("--ops-reps", type=int, default=10)
     ap.add_argument("--serve-requests", type=int, default=12,
