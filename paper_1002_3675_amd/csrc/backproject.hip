@@ -32,7 +32,7 @@ namespace cbct {
 namespace {
 
 constexpr int CB_X = 8, CB_Y = 8, CB_Z = 4;  // cells per workgroup
-constexpr int TABLE = 544;                    // pixels staged per view (26 KB)
+constexpr int TABLE = 464;                    // pixels staged per view (22 KB)
 constexpr int G_BX = 64, G_BY = 4;            // pass-2 block
 
 // Ray table entry per pixel and view (prepared once): the ray increment D
@@ -331,9 +331,11 @@ __device__ __forceinline__ void visit_global(T acc[8], const CellRange &cr, cons
     }
 }
 
-// Six workgroups of 256 lanes per CU: at most 80 VGPRs and 26 KB of LDS.
+// Seven workgroups of 256 lanes per CU: at most 72 VGPRs (a few values
+// live across the view loop spill, reloaded only after the rare unstaged
+// path) and 22.9 KB of LDS.
 template <typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_cells(const ViewConst *__restrict__ views, DetConst dc,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_cells(const ViewConst *__restrict__ views, DetConst dc,
                                                GridConst gc, int nu, int nv, int nviews,
                                                const PixelRay *__restrict__ rays,
                                                const int4 *__restrict__ rects,
