@@ -68,3 +68,33 @@ def test_budget_forces_queueing():
     assert srv.peak_used <= srv.budget
     assert srv.peak_active <= 2
     assert all(f.result().report.iters_done == 6 for f in futs)
+
+
+def test_mixed_schedules_equal_alone():
+    """Requests with three levels, a tolerance stop or the Eq. (2) gradient
+    share the GPU with plain ones; each result and its per-level iteration
+    counts equal the same request solved alone."""
+    torch = require_gpu()
+    import dataclasses
+    import paper_1002_3675_amd as cb
+    from paper_1002_3675_amd.serve import GpuExecutor, Server
+    reqs = _requests(8, seed=52)
+    variants = [dict(iters=(2, 2, 3)), dict(iters=(10, 10), tol=2e-2),
+                dict(gradient="eq2"), dict()]
+    for k, r in enumerate(reqs):
+        r.params = dataclasses.replace(r.params, **variants[k % 4])
+    ex = GpuExecutor(0)
+    alone = []
+    for r in reqs:
+        alone.append(cb.fbs_solve(ex.plan_for(r.geom), torch.as_tensor(r.Y, device="cuda"),
+                                  r.params))
+    torch.cuda.synchronize()
+    srv = Server(ex, hbm_budget=8 << 30, max_active=4, iters_per_tick=1)
+    futs = [srv.submit(r) for r in reqs]
+    srv.run_until_idle(timeout=300)
+    assert srv.peak_active >= 2
+    for fut, (want_f, want_rep) in zip(futs, alone):
+        res = fut.result()
+        torch.cuda.synchronize()
+        assert torch.equal(res.f, want_f), res.id
+        assert res.report.level_iters == want_rep.level_iters, res.id
