@@ -97,10 +97,17 @@ def eq2_comparison(torch, cb, plan, Y, params, f_matched, rep_matched, yr, fb, m
 def operator_rooflines(g, samples, ms_p, ms_pt):
     """P and P^T at the fine level against both ceilings: algorithmic HBM
     bytes (P: read the volume, write the projections; P^T: read the
-    projections, write the volume) over HBM peak, and 34 flop per ray
-    sample over the ALU peak."""
+    projections, write the volume) over HBM peak, the counter-measured HBM
+    bytes of the same kernels over HBM peak, and 34 flop per ray sample over
+    the ALU peak."""
     vol_b = 4.0 * g.n_vox
     proj_b = 4.0 * g.n_meas
+    # counter-measured HBM bytes of one fine launch (None while the kernel
+    # sources differ from the ones the counters were taken on)
+    fine = (0, 1)
+    cells, gather = measured_traffic("cells", fine), measured_traffic("gather", fine)
+    measured = {"P": measured_traffic("project", fine),
+                "PT": None if cells is None or gather is None else cells + gather}
     out = {}
     for name, ms in (("P", ms_p), ("PT", ms_pt)):
         gbs = (vol_b + proj_b) / (ms * 1e-3) / 1e9
@@ -109,6 +116,10 @@ def operator_rooflines(g, samples, ms_p, ms_pt):
                      "algorithmic_bytes": vol_b + proj_b, "hbm_gbs": gbs,
                      "hbm_frac": gbs / PEAK_HBM_GBS, "alu_tflops": tfl,
                      "alu_frac": tfl / PEAK_ALU_TFLOPS}
+        if measured[name] is not None:
+            mg = measured[name] / (ms * 1e-3) / 1e9
+            out[name].update({"measured_bytes": measured[name], "measured_hbm_gbs": mg,
+                              "measured_hbm_frac": mg / PEAK_HBM_GBS})
     return out
 
 
