@@ -11,7 +11,7 @@
 //   * preparation (geometry only, once per workspace): the ray increment
 //     of every pixel of every view, and every brick's pixel rectangle per
 //     view (its footprint on the detector);
-//   * pass 1 (one lane per cell, a workgroup per 8x8x4 brick of cells): for
+//   * pass 1 (one lane per cell, a workgroup per 8x16x2 brick of cells): for
 //     every view the workgroup copies the ray increments (double) and
 //     residuals of its brick's footprint into LDS; each lane then visits
 //     the pixels whose rays can cross its cell, enumerates the samples of
@@ -31,8 +31,8 @@ namespace cbct {
 
 namespace {
 
-constexpr int CB_X = 8, CB_Y = 8, CB_Z = 4;  // cells per workgroup
-constexpr int TABLE = 464;                    // pixels staged per view (22 KB)
+constexpr int CB_X = 8, CB_Y = 16, CB_Z = 2;  // cells per workgroup
+constexpr int TABLE = 448;                    // pixels staged per view (21 KB)
 constexpr int G_BX = 64, G_BY = 4;            // pass-2 block
 
 // Ray table entry per pixel and view (prepared once): the ray increment D
@@ -333,7 +333,7 @@ __device__ __forceinline__ void visit_global(T acc[8], const CellRange &cr, cons
 
 // Seven workgroups of 256 lanes per CU: at most 72 VGPRs (a few values
 // live across the view loop spill, reloaded only after the rare unstaged
-// path) and 22.9 KB of LDS.
+// path) and 22.7 KB of LDS.
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_cells(const ViewConst *__restrict__ views, DetConst dc,
                                                GridConst gc, int nu, int nv, int nviews,
@@ -382,15 +382,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
         __syncthreads();  // readers of the previous view are done
         // the brick's (CB_X + 1) x (CB_Y + 1) cell corners in the xy plane,
         // projected: u / sdd and 1 / depth (the corner expressions of
-        // box_footprint, shared by the 8 x 8 cells of every layer)
-        if (tid < (CB_X + 1) * (CB_Y + 1)) {
-            const int a = tid % (CB_X + 1), b = tid / (CB_X + 1);
+        // box_footprint, shared by the cells of every layer)
+        for (int t = tid; t < (CB_X + 1) * (CB_Y + 1); t += 256) {
+            const int a = t % (CB_X + 1), b = t / (CB_X + 1);
             const float x = gc.x0 + (float)(bb.c0[0] + a) * gc.hx;
             const float y = gc.y0 + (float)(bb.c0[1] + b) * gc.hy;
             const float wx = x - vc.src[0], wy = y - vc.src[1];
             const float n = wx * vc.cs + wy * vc.sn, d = wy * vc.cs - wx * vc.sn;
             const float ri = rcp(d);
-            corner[tid] = make_float2(n * ri, ri);
+            corner[t] = make_float2(n * ri, ri);
         }
         if (staged) {
             // element t -> (row, col) by a float reciprocal: exact for
