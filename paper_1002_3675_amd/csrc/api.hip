@@ -241,7 +241,7 @@ int validate_geom(const cbct_geom *g) {
     // the transpose stores cell indices and segment numbers as 16-bit integers
     if (g->nx > 32000 || g->ny > 32000 || g->nz > 32000)
         return set_error(CBCT_EINVAL, "grid dimension above 32000");
-    if (std::ceil(g->nu / 32.0) * std::ceil(g->nv / 8.0) * g->n_views > 2147483647.0)
+    if ((double)project_partials_count(*g) > 2147483647.0)
         return set_error(CBCT_EINVAL, "too many detector tiles");
     if (g->angles)
         for (int k = 0; k < g->n_views; ++k)
@@ -824,8 +824,7 @@ extern "C" size_t cbct_fbs_footprint(const cbct_geom *g, const cbct_fbs_params *
         b += level_bytes(c, true, prm->gradient, tol);
     }
     // partials and scalars
-    dim3 pg((g->nu + 31) / 32, (g->nv + 7) / 8, g->n_views);  // projector tile grid
-    size_t np = std::max((size_t)pg.x * pg.y * pg.z,
+    size_t np = std::max(project_partials_count(*g),
                          (size_t)2 * ((g->nx + 63) / 64) * ((g->ny + 3) / 4) * g->nz);
     if (tol) np = std::max(np, (size_t)2 * DIFF_BLOCKS);
     b += sizeof(double) * (np + 8);

@@ -113,6 +113,7 @@ hipError_t launch_eq2(const cbct_plan &p, const float *r, const float *f, double
 hipError_t launch_count_samples(const cbct_plan &p, unsigned long long *count, hipStream_t s);
 
 size_t project_partials_count(const cbct_plan &p);
+size_t project_partials_count(const cbct_geom &g);
 size_t padded_count(const cbct_plan &p);
 
 hipError_t launch_tv_sweep(const GridConst &gc, const float *z, const float *g, float *out,

@@ -1,8 +1,10 @@
 // Forward cone-beam projection P (Eq. (1)): ray-driven trilinear ray march.
 //
-// One lane per ray; a wavefront covers 64 neighbouring detector columns of
-// one row, so at equal sample index the 64 lanes touch neighbouring voxels
-// and the eight trilinear taps of the wave share cache lines.  The volume is
+// One lane per ray.  The float path (k_project_tile) gives a workgroup a
+// square tile of neighbouring rays and stages the volume boxes they cross in
+// LDS; the double path (k_project) lets a wavefront cover 64 neighbouring
+// detector columns of one row, so at equal sample index the 64 lanes touch
+// neighbouring voxels and the taps of the wave share cache lines.  The volume is
 // read from a copy with a one-voxel zero border, so every tap of every
 // sample the ray takes is in bounds without per-sample tests: the sample
 // interval is computed exactly (cell of every sample in [-1, N-1]).  Float
@@ -159,7 +161,7 @@ __device__ __forceinline__ double march_double(const double Q[3], const double D
 }
 
 // ---------------------------------------------------------------------------
-// Float projector with LDS-staged volume.  A workgroup owns a 32 x 8 tile of
+// Float projector with LDS-staged volume.  A workgroup owns a 16 x 16 tile of
 // detector pixels of one view; its 256 rays advance together through
 // chunks of TILE_CH consecutive sample indices.  For each chunk the four
 // corner rays of the tile bound (with a margin for the curvature of the
@@ -167,8 +169,11 @@ __device__ __forceinline__ double march_double(const double Q[3], const double D
 // of the zero-bordered volume is staged in LDS with row-coalesced loads and
 // the eight trilinear taps of every sample are read from LDS.  A chunk whose
 // box does not fit falls back to loads from global memory.  The samples,
-// their cells and weights are exactly those of march_float.
-constexpr int TILE_U = 32, TILE_V = 8, TILE_CH = 16;
+// their cells and weights are exactly those of march_float.  A square tile
+// keeps the bundle, and so the box, narrow in both detector directions;
+// 32-sample chunks then still fit 16 KB and spread the per-chunk box and
+// segment-origin work over twice the samples.
+constexpr int TILE_U = 16, TILE_V = 16, TILE_CH = 32;
 constexpr int TILE_LDS = 4096;  // floats
 
 __global__ __launch_bounds__(256) void k_project_tile(
@@ -382,11 +387,12 @@ dim3 project_grid(const cbct_plan &p) {
     return dim3((p.g.nu + PROJ_BX - 1) / PROJ_BX, (p.g.nv + PROJ_BY - 1) / PROJ_BY, p.g.n_views);
 }
 
-// One-dimensional grid of all tiles of all views (see xcd_tile).
-dim3 tile_grid(const cbct_plan &p) {
-    return dim3((unsigned)((p.g.nu + TILE_U - 1) / TILE_U) * ((p.g.nv + TILE_V - 1) / TILE_V) *
-                p.g.n_views);
+size_t tile_count(const cbct_geom &g) {
+    return (size_t)((g.nu + TILE_U - 1) / TILE_U) * ((g.nv + TILE_V - 1) / TILE_V) * g.n_views;
 }
+
+// One-dimensional grid of all tiles of all views (see xcd_tile).
+dim3 tile_grid(const cbct_plan &p) { return dim3((unsigned)tile_count(p.g)); }
 
 // Cells of margin around the corner rays' box: the samples of rays inside a
 // tile deviate from the corner rays' hull by at most t (1 - cos a) ~ t a^2/2,
@@ -406,9 +412,8 @@ int tile_margin(const cbct_plan &p) {
 
 // Partial sums written by a float projection (one per workgroup of the
 // tile grid); the double projector takes no partials.
-size_t project_partials_count(const cbct_plan &p) {
-    return (size_t)tile_grid(p).x;
-}
+size_t project_partials_count(const cbct_plan &p) { return tile_count(p.g); }
+size_t project_partials_count(const cbct_geom &g) { return tile_count(g); }
 
 size_t padded_count(const cbct_plan &p) {
     return (size_t)(p.g.nx + 2) * (p.g.ny + 2) * (p.g.nz + 2);
