@@ -92,3 +92,22 @@ def test_tolerance_stop_matches_oracle():
     # two levels, a tolerance no iteration meets: the counts are maxima
     _, rep = cb.fbs_solve(plan, to_dev(Y), cb.FbsParams(mu=mu, iters=(2, 3), tol=1e-9))
     assert rep.level_iters == (2, 3)
+
+
+def test_single_plane_coarse_level_matches_oracle():
+    """Three planes coarsen to one (and 21 columns to 10, half a spacing off
+    the axis): the coarse level is a single slab of cells."""
+    require_gpu()
+    import paper_1002_3675_amd as cb
+    _log("single-plane coarse level")
+    g = Geometry(21, 18, 3, 4.0, 4.0, 5.0, 40, 12, 3.2, 3.2, 1000.0, 1500.0, 8)
+    mu = 1e-3
+    Y = _data(g, 90).astype(np.float32).astype(np.float64)
+    setup = oracle.fbs_solve(g, Y, mu, (0, 0))
+    beta, inner = tuple(setup["used_beta"]), tuple(int(k) for k in setup["used_inner"])
+    want = oracle.fbs_solve(g, Y, mu, (3, 3), beta=beta, n_inner=inner, trace=True)
+    f, rep = cb.fbs_solve(cb.Plan(g), to_dev(Y),
+                          cb.FbsParams(mu=mu, iters=(3, 3), beta=beta, n_inner=inner,
+                                       trace_energy=True))
+    assert rel_l2(to_np(f), want["f"]) <= 1e-3, rel_l2(to_np(f), want["f"])
+    assert abs(rep.E - want["report"][0]) <= 1e-4 * abs(want["report"][0])
