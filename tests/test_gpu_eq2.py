@@ -79,3 +79,24 @@ def test_fbs_eq2_mode_matches_oracle():
     E = want["report"][0]
     assert abs(rep.E - E) <= 1e-4 * abs(E), (rep.E, E)
     assert float(f.min()) >= 0.0
+
+
+def test_eq2_head_size_two_views():
+    """Full 512x512x70 Eq. (2) operator on the 40-view head geometry with
+    data on two views (the others zero), against the oracle on those two."""
+    require_gpu()
+    import dataclasses
+    import math
+    import paper_1002_3675_amd as cb
+    from workloads import head_geometry
+    _log("eq2 head size")
+    g = head_geometry(40)
+    rng = np.random.default_rng(33)
+    y = np.zeros(g.proj_shape, dtype=np.float32)
+    ks = (3, 22)
+    for k in ks:
+        y[k] = rng.uniform(-1.0, 4.0, (g.nv, g.nu))
+    got = to_np(cb.Plan(g).backproject_eq2(to_dev(y)))
+    gk = dataclasses.replace(g, n_views=2, angles=tuple(2 * math.pi * k / 40 for k in ks))
+    want = oracle.eq2_backproject(gk, y[list(ks)].astype(np.float64))
+    assert rel_l2(got, want) <= 1e-5, rel_l2(got, want)
