@@ -73,7 +73,8 @@ def diff_inputs(fd: bool = False, seed: int = 3000):
 
 def fov_mask(g: Geometry) -> np.ndarray:
     """Voxels inside the transaxial field of view seen by every view and the
-    axial range seen by every view (boolean, (nz, ny, nx))."""
+    axial range seen by every view (boolean, (nz, ny, nx)), for a centred
+    detector (u_off = v_off = 0) over a full turn."""
     half_u = g.nu * g.au / 2.0
     fov_r = g.sad * half_u / math.hypot(g.sdd, half_u)
     x = (np.arange(g.nx) - (g.nx - 1) / 2.0) * g.hx + g.x_off
