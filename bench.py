@@ -131,7 +131,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=16,
                     help="views of the head scan the CPU oracle sample uses")
-    ap.add_argument("--ops-reps", type=int, default=10)
+    ap.add_argument("--ops-reps", type=int, default=20,
+                    help="timed launches per stand-alone operator (median reported)")
     ap.add_argument("--serve-requests", type=int, default=12,
                     help="requests in the served mixed stream (0 skips it)")
     ap.add_argument("--serve-load", type=float, default=0.8,
@@ -159,18 +160,23 @@ def coarse_of(g):
                                step=2 * (g.step if g.step > 0 else 0.5 * min(g.hx, g.hy, g.hz)))
 
 
-def time_op(torch, fn, reps):
+def time_op(torch, fn, reps, warmup=3):
+    """Median over `reps` launches of fn, each bracketed by its own pair of
+    HIP events on the current stream (the stream the library launches on),
+    after `warmup` untimed launches."""
+    import statistics
     s = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    fn()
-    torch.cuda.synchronize()
-    e0.record(s)
-    for _ in range(reps):
+    for _ in range(warmup):
         fn()
-    e1.record(s)
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(max(1, reps))]
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps
+    for e0, e1 in events:
+        e0.record(s)
+        fn()
+        e1.record(s)
+    torch.cuda.synchronize()
+    return statistics.median(e0.elapsed_time(e1) for e0, e1 in events)
 
 
 def cpu_baseline(case_geom, Y, views):
