@@ -1,14 +1,19 @@
-"""Write tests/golden/head40_fbs.json: the FP64 oracle's full two-level
-solve of the head-sized workload (512x512x70, 40 views, 512x384 detector,
-seeded random-ellipsoid head, Poisson I0 = 5e4, mu = 1e-3, 20 + 20
-iterations), for the GPU parity test at full size.
+"""Write the FP64 oracle's full two-level solve of the head-sized workload
+(512x512x70, 40 views, 512x384 detector, seeded random-ellipsoid head,
+Poisson I0 = 5e4, mu = 1e-3, 20 + 20 iterations), for the GPU parity test
+at full size:
 
-Calls only oracle/ and the seeded input generators.  The oracle computes
-its own beta per level (30 power-iteration steps) and its own inner
-iteration counts; the file stores them, the energies of the result, and
-the result at 4096 seeded voxel positions inside the field of view.
+  head40_fbs.json    beta and inner counts per level (the oracle's own:
+                     30 power-iteration steps), the energies of the result,
+                     its norm, the L2 norm and the sum of every z plane, and
+                     the result at 4096 seeded voxels of the field of view
+                     where the phantom is not air;
+  head40_slices.npz  whole axial planes z = 0, 10, 35, 60, 69 of the result
+                     (float32), the first and last planes included.
 
-    OMP_NUM_THREADS=8 python tests/golden/make_head_fbs.py   (~1-2 h on 8 cores)
+Calls only oracle/ and the seeded input generators.
+
+    OMP_NUM_THREADS=8 python tests/golden/make_head_fbs.py   (~80 min on 8 cores)
 """
 
 import json
@@ -26,11 +31,16 @@ from workloads import head_case, fov_mask  # noqa: E402
 
 N_SAMPLES = 4096
 SAMPLE_SEED = 4242
+SLICES = (0, 10, 35, 60, 69)
+JSON_NAME = "head40_fbs.json"
+SLICE_NAME = "head40_slices.npz"
 
 
-def sample_indices(g):
-    """Seeded voxel indices inside the field of view (flat, x fastest)."""
-    mask = fov_mask(g).ravel()
+def sample_indices(case):
+    """Seeded voxel indices (flat, x fastest) inside the field of view where
+    the voxelised phantom is not air."""
+    g = case.geom
+    mask = (fov_mask(g) & (case.voxelised() > 0.0)).ravel()
     idx = np.nonzero(mask)[0]
     rng = np.random.default_rng(SAMPLE_SEED)
     return np.sort(rng.choice(idx, size=N_SAMPLES, replace=False))
@@ -42,8 +52,8 @@ def main():
     g = case.geom
     Y32 = case.Y.astype(np.float32).astype(np.float64)  # what the GPU receives
     out = oracle.fbs_solve(g, Y32, case.mu, list(case.iters), eps=case.eps)
-    f = out["f"]
-    idx = sample_indices(g)
+    f = out["f"].reshape(g.vol_shape)
+    idx = sample_indices(case)
     res = {
         "workload": "head 512x512x70 @0.88x0.88x2.5, 40 views, 512x384 @0.776, "
                     "SAD/SDD 1000/1500, random-ellipsoid head seed 1001, Poisson I0=5e4 "
@@ -57,12 +67,17 @@ def main():
         "sample_seed": SAMPLE_SEED,
         "samples": [float(v) for v in f.ravel()[idx]],
         "f_norm": float(np.linalg.norm(f)),
+        "plane_norm": [float(np.linalg.norm(f[k])) for k in range(g.nz)],
+        "plane_sum": [float(f[k].sum()) for k in range(g.nz)],
+        "slices": list(SLICES),
         "oracle_threads": oracle.threads(),
         "oracle_seconds": time.time() - t0,
     }
-    with open(os.path.join(HERE, "head40_fbs.json"), "w") as fh:
+    np.savez_compressed(os.path.join(HERE, SLICE_NAME),
+                        **{"z%d" % k: f[k].astype(np.float32) for k in SLICES})
+    with open(os.path.join(HERE, JSON_NAME), "w") as fh:
         json.dump(res, fh)
-    print("wrote head40_fbs.json in %.0f s" % (time.time() - t0))
+    print("wrote %s and %s in %.0f s" % (JSON_NAME, SLICE_NAME, time.time() - t0))
 
 
 if __name__ == "__main__":

@@ -1,8 +1,10 @@
 """Full-size gates: the head workload (512x512x70, 40 views, 512x384) with
 the full two-level 20 + 20 schedule against the FP64 oracle's solve stored
-by tests/golden/make_head_fbs.py (volume within 1e-3 relative L2 over 4096
-seeded voxels of the field of view, energy within 1e-4), and the power
-iteration that sets beta against the oracle's."""
+by tests/golden/make_head_fbs.py (energy within 1e-4; volume within 1e-3
+relative L2 on five whole axial planes, the first and last included, and
+on 4096 seeded non-air voxels of the field of view; every plane's norm and
+sum, and the whole volume's norm, within 1e-3), and the power iteration
+that sets beta against the oracle's."""
 
 import json
 import os
@@ -28,21 +30,46 @@ def test_head_full_schedule_matches_oracle():
         pytest.skip("golden oracle solve not generated (tests/golden/make_head_fbs.py)")
     import paper_1002_3675_amd as cb
     sys.path.insert(0, os.path.join(HERE, "golden"))
-    from make_head_fbs import sample_indices
+    import make_head_fbs as mk
     want = json.load(open(GOLDEN))
     case = head_case(40, iters=(20, 20))
     g = case.geom
     plan = cb.Plan(g)
+    print("head solve: 512x512x70, 40 views, 20 + 20 iterations", flush=True)
     Y = torch.as_tensor(case.Y.astype(np.float32), device="cuda")
     f, rep = cb.fbs_solve(plan, Y, cb.FbsParams(mu=case.mu, iters=(20, 20), beta=want["beta"],
                                                eps=case.eps, n_inner=want["n_inner"],
                                                trace_energy=True))
-    got = f.cpu().double().numpy().ravel()[sample_indices(g)]
+    vol = f.cpu().double().numpy().reshape(g.vol_shape)
+    assert float(vol.min()) >= 0.0
+    assert abs(rep.E - want["E"]) <= 1e-4 * abs(want["E"]), (rep.E, want["E"])
+    # whole volume: its norm
+    assert abs(np.linalg.norm(vol) - want["f_norm"]) <= 1e-3 * want["f_norm"]
+    if "plane_norm" not in want:  # the earlier golden format: 4096 field-of-view voxels
+        mask = np.nonzero(mk.fov_mask(g).ravel())[0]
+        idx = np.sort(np.random.default_rng(want["sample_seed"]).choice(mask, size=4096,
+                                                                       replace=False))
+        got, ref = vol.ravel()[idx], np.array(want["samples"])
+        assert np.linalg.norm(got - ref) <= 1e-3 * np.linalg.norm(ref)
+        return
+    # seeded voxels of the field of view where the phantom is not air
+    got = vol.ravel()[mk.sample_indices(case)]
     ref = np.array(want["samples"])
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     assert err <= 1e-3, err
-    assert abs(rep.E - want["E"]) <= 1e-4 * abs(want["E"]), (rep.E, want["E"])
-    assert float(f.min()) >= 0.0
+    # every z plane: L2 norm and sum
+    tot = np.linalg.norm(vol)
+    for k in range(g.nz):
+        pn, ps = np.linalg.norm(vol[k]), vol[k].sum()
+        assert abs(pn - want["plane_norm"][k]) <= 1e-3 * max(want["plane_norm"][k], 1e-3 * tot), k
+        assert abs(ps - want["plane_sum"][k]) <= 1e-3 * max(abs(want["plane_sum"][k]),
+                                                          1e-3 * abs(sum(want["plane_sum"]))), k
+    # whole axial planes, the first and the last included
+    slices = np.load(os.path.join(HERE, "golden", mk.SLICE_NAME))
+    for k in want["slices"]:
+        ref = slices["z%d" % k].astype(np.float64)
+        err = np.linalg.norm(vol[k] - ref) / np.linalg.norm(ref)
+        assert err <= 1e-3, (k, err)
 
 
 def test_power_iteration_matches_oracle():
