@@ -156,6 +156,22 @@ int cbct_tv_prox(const cbct_geom *grid, const float *g, float *f, double beta,
                  double eps, int32_t n_inner, double step, int32_t nonneg,
                  void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sweeps as cbct_tv_prox, same arguments and results bit for bit, with its
+ * ping-pong volume in a fixed library array of 2^24 floats (64 MiB) held on
+ * every GPU the library runs on until the process ends.  Grids of more
+ * than 2^24 voxels give EINVAL (use cbct_tv_prox).  No device memory is
+ * allocated or freed; the first call on a device looks up the array's
+ * device address (EHIP if that fails), so make one call on each device
+ * before capturing.  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents: calls that overlap on one GPU (different
+ * streams, or threads) race and must be serialised by the caller.  The
+ * launches are not recorded by cbct_kernel_timing. */
+int cbct_tv_prox_noalloc(const cbct_geom *grid, const float *g, float *f, double beta,
+                         double eps, int32_t n_inner, double step, int32_t nonneg,
+                         void *stream);
+
 /* E1 of Eq. (1) on the grid: out_host[0] = mean_v |Df|_v, out_host[1] =
  * mean_v sqrt(|Df|_v^2 + eps^2).  Synchronises `stream`. */
 int cbct_tv_energy(const cbct_geom *grid, const float *f, double eps,

@@ -238,17 +238,26 @@ def _grid_c(shape, h):
                      2.0, 3.0, 1, None, 0.0)
 
 
-def tv_prox(g, z0, h, beta, eps, n_inner, step=0.0, nonneg=True):
-    """Steps 2-3 of Algorithm A1 on the GPU; returns z (new tensor)."""
+def tv_prox(g, z0, h, beta, eps, n_inner, step=0.0, nonneg=True, noalloc=False, out=None):
+    """Steps 2-3 of Algorithm A1 on the GPU; returns z (a new tensor, or
+    `out` filled).  noalloc=True calls cbct_tv_prox_noalloc (no device
+    allocation in the library; grids up to 2^24 voxels)."""
     torch = _torch()
     _check_tensor(g, g.shape, torch.float32, "g")
     _check_tensor(z0, g.shape, torch.float32, "z0")
-    z = z0.clone()
+    if out is None:
+        z = z0.clone()
+    else:
+        _check_tensor(out, g.shape, torch.float32, "out")
+        z = out
+        if z.data_ptr() != z0.data_ptr():
+            z.copy_(z0)
     c = _grid_c(g.shape, h)
+    name = "cbct_tv_prox_noalloc" if noalloc else "cbct_tv_prox"
     with torch.cuda.device(g.device):
-        check(_native.lib().cbct_tv_prox(ctypes.byref(c), _ptr(g), _ptr(z), float(beta),
-                                         float(eps), int(n_inner), float(step), int(bool(nonneg)),
-                                         _stream_of(g)), "cbct_tv_prox")
+        check(getattr(_native.lib(), name)(ctypes.byref(c), _ptr(g), _ptr(z), float(beta),
+                                           float(eps), int(n_inner), float(step),
+                                           int(bool(nonneg)), _stream_of(g)), name)
     return z
 
 

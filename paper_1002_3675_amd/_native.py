@@ -66,6 +66,8 @@ SIGNATURES = {
     "cbct_project_f64": (ctypes.c_int, [_P, _P, _P, _P]),
     "cbct_backproject_f64": (ctypes.c_int, [_P, _P, _P, _P]),
     "cbct_tv_prox": (ctypes.c_int, [ctypes.POINTER(cbct_geom), _P, _P, _D, _D, _I32, _D, _I32, _P]),
+    "cbct_tv_prox_noalloc": (ctypes.c_int, [ctypes.POINTER(cbct_geom), _P, _P, _D, _D, _I32,
+                                            _D, _I32, _P]),
     "cbct_tv_energy": (ctypes.c_int, [ctypes.POINTER(cbct_geom), _P, _D,
                                       ctypes.POINTER(_D), _P]),
     "cbct_plan_lambda": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_D), _P]),

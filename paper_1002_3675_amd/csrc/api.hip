@@ -493,12 +493,17 @@ int default_inner(const cbct_geom &g, double beta, double eps) {
 }
 
 // K sweeps from z0 = f (in place), ping-ponging with `tmp` (nvox floats).
+// `timing` = false launches without the diagnostic HIP events (whose
+// creation the no-allocation entry point must not make).
 int prox_sweeps(const GridConst &gc, size_t nvox, const float *g, float *f, float *tmp,
-                double beta, double eps, int n_inner, double step, int nonneg, hipStream_t s) {
+                double beta, double eps, int n_inner, double step, int nonneg, hipStream_t s,
+                bool timing = true) {
     float *a = f, *b = tmp;
     for (int m = 0; m < n_inner; ++m) {
-        int rc = check_hip(timed(CBCT_KERNEL_TV_SWEEP, s, [&] { return launch_tv_sweep(gc, a, g, b, (float)beta, (float)eps, (float)step,
-                                           nonneg, s); }),
+        auto launch = [&] {
+            return launch_tv_sweep(gc, a, g, b, (float)beta, (float)eps, (float)step, nonneg, s);
+        };
+        int rc = check_hip(timing ? timed(CBCT_KERNEL_TV_SWEEP, s, launch) : launch(),
                            "tv sweep");
         if (rc) return rc;
         std::swap(a, b);
@@ -539,6 +544,66 @@ extern "C" int cbct_tv_prox(const cbct_geom *grid, const float *g, float *f, dou
         if (rc) return rc;
         return prox_sweeps(grid_of(*grid), nvox, g, f, tmp.as<float>(), beta, eps, n_inner, step,
                            nonneg, s);
+    } catch (...) {
+        return set_error(CBCT_EHIP, "unexpected exception");
+    }
+}
+
+// ------------------------------------------- no-allocation TV prox ---
+// The ping-pong volume of cbct_tv_prox_noalloc lives in this fixed device
+// array, one copy per GPU.  Host code never passes the array's name to a
+// kernel or a copy (on the host it is only a stand-in): it looks up the
+// device address once per device with hipGetSymbolAddress and uses that.
+constexpr size_t NOALLOC_MAX_VOXELS = size_t(1) << 24;  // 64 MiB of float
+
+static __device__ __align__(256) float scratch[NOALLOC_MAX_VOXELS];
+
+namespace {
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[64] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call per device.  EHIP if the lookup fails.
+int scratch_address(float **out) {
+    int dev = 0;
+    int rc = check_hip(hipGetDevice(&dev), "current device");
+    if (rc) return rc;
+    if (dev < 0 || dev >= 64) return set_error(CBCT_EHIP, "device index above 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        rc = check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "scratch symbol address");
+        if (rc) return rc;
+        g_scratch_ptr[dev] = static_cast<float *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return CBCT_OK;
+}
+}  // namespace
+
+extern "C" int cbct_tv_prox_noalloc(const cbct_geom *grid, const float *g, float *f,
+                                    double beta, double eps, int32_t n_inner, double step,
+                                    int32_t nonneg, void *stream) {
+    try {
+        int rc = validate_grid(grid);
+        if (rc) return rc;
+        if (!g || !f) return set_error(CBCT_EINVAL, "NULL argument");
+        if (!(beta > 0) || !(eps > 0) || n_inner < 0 || !isfinite(beta) || !isfinite(eps))
+            return set_error(CBCT_EINVAL, "need beta > 0, eps > 0, n_inner >= 0");
+        const size_t nvox = nvox_of(*grid);
+        if (nvox > NOALLOC_MAX_VOXELS)
+            return set_error(CBCT_EINVAL, "cbct_tv_prox_noalloc: grid of " +
+                                              std::to_string(nvox) +
+                                              " voxels exceeds its fixed scratch of " +
+                                              std::to_string(NOALLOC_MAX_VOXELS) +
+                                              " voxels; use cbct_tv_prox");
+        float *tmp = nullptr;
+        rc = scratch_address(&tmp);
+        if (rc) return rc;
+        if (n_inner == 0) return CBCT_OK;
+        if (!(step > 0)) step = default_prox_step(*grid, beta, eps);
+        return prox_sweeps(grid_of(*grid), nvox, g, f, tmp, beta, eps, n_inner, step, nonneg,
+                           as_stream(stream), false);
     } catch (...) {
         return set_error(CBCT_EHIP, "unexpected exception");
     }
