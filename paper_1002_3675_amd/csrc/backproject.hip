@@ -27,12 +27,16 @@
 // another lane writes.
 #include "ray.hpp"
 
+#ifndef CBCT_CELL_TABLE
+#define CBCT_CELL_TABLE 344
+#endif
+
 namespace cbct {
 
 namespace {
 
-constexpr int CB_X = 8, CB_Y = 16, CB_Z = 2;  // cells per workgroup
-constexpr int TABLE = 448;                    // pixels staged per view (21 KB)
+constexpr int CB_X = 16, CB_Y = 16, CB_Z = 1;  // cells per workgroup: one z layer
+constexpr int TABLE = CBCT_CELL_TABLE;         // pixels staged per view (60 B each)
 constexpr int G_BX = 64, G_BY = 4;            // pass-2 block
 
 // Ray table entry per pixel and view (prepared once): the ray increment D
@@ -45,19 +49,41 @@ struct PixelRay {
     float pad;
 };
 
-// LDS entry per footprint pixel of the current view: the origin (I, f) of
-// the segment sq * SEG that holds the ray's first sample in the brick, as
-// the projector computes it; D_f = (float)D; the reciprocals; the residual.
-// Cells whose samples of this ray start in another segment compute that
-// segment's origin from the ray table.  48 bytes.  Grid dimensions below
-// 32000 keep I (within SEG/2 + 2 cells of the brick) in a short.
-struct StagedRay {
-    short I[3];
-    short sq;
+// LDS entry per footprint pixel of the current view, in two parts.
+//
+// StagedRange serves the candidate test every cell of the brick makes for
+// this pixel.  Along axis a the samples with coordinate in [c_a, c_a + 1)
+// lie between (c_a - Q_a)/D_a and (c_a + 1 - Q_a)/D_a.  The float Q and D
+// differ from the double ones by at most ~1e-6 relative, which moves these
+// bounds by at most 1e-6 (|Q_a| + |c_a| + 1) |inv_a| (inv = 1/D_f); a
+// margin m_a = K_a |inv_a| + 1e-3 with K_a = 4e-6 (|Q_a| + max |c_a| over
+// the brick + 1) covers four times that plus the rounding of the float
+// estimate itself.  With the cell's cq_a = c_a - Q_a (float) the widened
+// bounds are
+//     lo_a = fma(cq_a, inv_a, min(0, inv_a) - m_a),
+//     hi_a = lo_a + |inv_a| (1 + 2 K_a) + 2e-3,
+// and lo[a] holds the additive term of lo_a (a = x, y).  Every cell of the
+// brick lies in the same z layer, so the z bounds are the same for all of
+// them: zlo, zhi.  24 bytes.
+//
+// StagedWalk serves the cells with candidates: the origin (I, f) of the
+// segment sq * SEG that holds the ray's first sample in the brick, as the
+// projector computes it; D_f = (float)D; the residual.  Cells whose
+// candidates start in another segment compute that segment's origin from
+// the ray table.  Grid dimensions below 32000 keep I (within SEG/2 + 2
+// cells of the brick) in a short.  36 bytes.
+struct StagedRange {
+    float inv[2];
+    float lo[2];
+    float zlo, zhi;
+};
+
+struct StagedWalk {
     float f[3];
     float Df[3];
-    float inv[3];
     float r;
+    short I[3];
+    short sq;
 };
 
 __device__ __forceinline__ float inv_or_huge(float d) {
@@ -163,12 +189,58 @@ __device__ __forceinline__ void add_corners(T acc[8], T rv, T wx, T wy, T wz) {
     t = a11 * wx; acc[6] += a11 - t; acc[7] += t;
 }
 
+// Float accumulation of r * corner weights in x-moment form: for each
+// (y, z) corner pair q = oy + 2 oz the cell keeps S_q = sum p_q and
+// T_q = sum p_q wx, p_q = r * (y weight) * (z weight); the corners are
+// (ox = 0) S_q - T_q and (ox = 1) T_q (moments_to_corners).  14 operations
+// per sample instead of 22.  The difference S_q - T_q carries an absolute
+// error of a few ulp of S_q, the cell's whole (y, z) mass, which is at most
+// the sum over the corners the voxel gather adds it to.
+__device__ __forceinline__ void add_moments(float acc[8], float rv, float wx, float wy,
+                                            float wz) {
+    const float b1 = rv * wz, b0 = rv - b1;
+    const float a01 = b0 * wy, a00 = b0 - a01;
+    const float a11 = b1 * wy, a10 = b1 - a11;
+    acc[0] += a00;
+    acc[1] = __builtin_fmaf(a00, wx, acc[1]);
+    acc[2] += a01;
+    acc[3] = __builtin_fmaf(a01, wx, acc[3]);
+    acc[4] += a10;
+    acc[5] = __builtin_fmaf(a10, wx, acc[5]);
+    acc[6] += a11;
+    acc[7] = __builtin_fmaf(a11, wx, acc[7]);
+}
+
+// Corner sums (index ox + 2 oy + 4 oz) from the x-moments of add_moments.
+__device__ __forceinline__ void moments_to_corners(const float m[8], float c[8]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        c[2 * q] = m[2 * q] - m[2 * q + 1];
+        c[2 * q + 1] = m[2 * q + 1];
+    }
+}
+
+// Where a pixel's ray-table entry is, computed only on the rare path that
+// needs the ray's double increment.  The pixel index passes through an
+// empty asm statement first, so the compiler cannot hoist the 64-bit
+// address arithmetic out of that path into every visit.
+struct RayRef {
+    const PixelRay *view;  // the view's table
+    int nu, i, j;
+    __device__ __forceinline__ const PixelRay *get() const {
+        int jj = j, ii = i;
+        asm volatile("" : "+v"(jj), "+v"(ii));
+        return view + ((long long)jj * nu + ii);
+    }
+};
+
 // Samples n0..n1 of a ray that fall in cell (cx, cy, cz), float data: o is
 // the origin of segment ns = n0 & ~(SEG - 1); a later segment's origin is
-// computed from the ray's double increment in the ray table (gray).  The
-// projector's own cell arithmetic decides membership.
+// computed from the ray's double increment in the ray table.  The
+// projector's own cell arithmetic decides membership; a candidate outside
+// the cell adds zero (no branch in the loop body).
 __device__ __forceinline__ void cell_samples_f(float acc[8], float rv, const double Qd[3],
-                                               const PixelRay *gray, SegOrigin o, int ns,
+                                               const RayRef &ray, SegOrigin o, int ns,
                                                const float Df[3], int n0, int n1, int cx,
                                                int cy, int cz) {
 #pragma clang fp contract(off)
@@ -193,13 +265,13 @@ __device__ __forceinline__ void cell_samples_f(float acc[8], float rv, const dou
             const float lz = __builtin_fmaf(m, Df[2], o.f[2]);
             const bool in = (__builtin_floorf(lx) == L[0]) & (__builtin_floorf(ly) == L[1]) &
                             (__builtin_floorf(lz) == L[2]);
-            if (!in) continue;
-            add_corners<float>(acc, rv, lx - L[0], ly - L[1], lz - L[2]);
+            add_moments(acc, in ? rv : 0.0f, lx - L[0], ly - L[1], lz - L[2]);
         }
         if (nend >= n1) return;
         // rare: the cell's samples of this ray run into the next segment
         ns += SEG;
         m = 0.0f;
+        const PixelRay *gray = ray.get();
         const double D[3] = {gray->D[0], gray->D[1], gray->D[2]};
         o = seg_origin(Qd, D, ns);
         bounds();
@@ -290,16 +362,25 @@ __global__ __launch_bounds__(256) void k_brick_rects(const ViewConst *__restrict
 }
 
 // Accumulate the samples of one ray (residual rv) that fall in the cell:
-// from an LDS entry (float data) or from the ray table (either type).
-__device__ __forceinline__ void visit_staged(float acc[8], const CellRange &cr,
-                                             const StagedRay &e, const PixelRay *gray,
-                                             const double Qd[3], int cx, int cy, int cz) {
-    const float inv[3] = {e.inv[0], e.inv[1], e.inv[2]};
-    int n0, n1;
-    if (!candidates_inv(cr, inv, n0, n1)) return;
+// from the LDS entries (float data) or from the ray table (either type).
+__device__ __forceinline__ void visit_staged(float acc[8], const float cq[2], const float kw[2],
+                                             const StagedRange &er, const StagedWalk *ew,
+                                             const RayRef &ray, const double Qd[3], int cx,
+                                             int cy, int cz) {
+    const float lx = __builtin_fmaf(cq[0], er.inv[0], er.lo[0]);
+    const float ly = __builtin_fmaf(cq[1], er.inv[1], er.lo[1]);
+    const float hx = lx + __builtin_fmaf(fabsf(er.inv[0]), kw[0], 2e-3f);
+    const float hy = ly + __builtin_fmaf(fabsf(er.inv[1]), kw[1], 2e-3f);
+    const float lo = fmaxf(fmaxf(lx, ly), er.zlo);
+    const float hi = fminf(fminf(hx, hy), er.zhi);
+    if (!(lo <= hi)) return;
+    const int n0 = clamp_to_int(-floor_t(-lo));
+    const int n1 = clamp_to_int(floor_t(hi));
+    if (n0 > n1) return;
     const int ns = n0 & ~(SEG - 1);
+    const StagedWalk &e = *ew;
     SegOrigin o;
-    if (ns == (int)e.sq * SEG) {
+    if ((n0 >> 8) == (int)e.sq) {
         o.I[0] = e.I[0];
         o.I[1] = e.I[1];
         o.I[2] = e.I[2];
@@ -307,16 +388,18 @@ __device__ __forceinline__ void visit_staged(float acc[8], const CellRange &cr,
         o.f[1] = e.f[1];
         o.f[2] = e.f[2];
     } else {
+        const PixelRay *gray = ray.get();
         const double D[3] = {gray->D[0], gray->D[1], gray->D[2]};
         o = seg_origin(Qd, D, ns);
     }
     const float Df[3] = {e.Df[0], e.Df[1], e.Df[2]};
-    cell_samples_f(acc, e.r, Qd, gray, o, ns, Df, n0, n1, cx, cy, cz);
+    cell_samples_f(acc, e.r, Qd, ray, o, ns, Df, n0, n1, cx, cy, cz);
 }
 
 template <typename T>
-__device__ __forceinline__ void visit_global(T acc[8], const CellRange &cr, const PixelRay *gray,
+__device__ __forceinline__ void visit_global(T acc[8], const CellRange &cr, const RayRef &ray,
                                              T rv, const double Qd[3], int cx, int cy, int cz) {
+    const PixelRay *gray = ray.get();
     const float inv[3] = {gray->inv[0], gray->inv[1], gray->inv[2]};
     int n0, n1;
     if (!candidates_inv(cr, inv, n0, n1)) return;
@@ -325,15 +408,15 @@ __device__ __forceinline__ void visit_global(T acc[8], const CellRange &cr, cons
         const int ns = n0 & ~(SEG - 1);
         float Df[3];
         to_float3(D, Df);
-        cell_samples_f(acc, rv, Qd, gray, seg_origin(Qd, D, ns), ns, Df, n0, n1, cx, cy, cz);
+        cell_samples_f(acc, rv, Qd, ray, seg_origin(Qd, D, ns), ns, Df, n0, n1, cx, cy, cz);
     } else {
         cell_samples_d(acc, rv, Qd, D, n0, n1, cx, cy, cz);
     }
 }
 
-// Seven workgroups of 256 lanes per CU: at most 72 VGPRs (a few values
-// live across the view loop spill, reloaded only after the rare unstaged
-// path) and 22.7 KB of LDS.
+// Workgroups of 256 lanes, one per brick.  Seven share a CU: 22.9 KB of
+// LDS (60 bytes per staged pixel and the brick's projected corners) and at
+// most 72 VGPRs.
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_cells(const ViewConst *__restrict__ views, DetConst dc,
                                                GridConst gc, int nu, int nv, int nviews,
@@ -341,7 +424,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
                                                const int4 *__restrict__ rects,
                                                const T *__restrict__ r, T *__restrict__ cells,
                                                T step) {
-    __shared__ StagedRay table[TABLE];
+    __shared__ StagedRange trange[TABLE];
+    __shared__ StagedWalk twalk[TABLE];
     __shared__ float2 corner[(CB_X + 1) * (CB_Y + 1)];
     const int tid = threadIdx.x;
     // bricks x-fastest, then y, then z; each XCD takes one contiguous range,
@@ -351,8 +435,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
     const int nb = gridDim.x;
     const int brick = xcd_tile(blockIdx.x, nb);
     const BrickBox bb = brick_box(gc, brick % nbx, (brick / nbx) % nby, brick / (nbx * nby));
-    const int cx = bb.c0[0] + (tid & (CB_X - 1));
-    const int cy = bb.c0[1] + ((tid / CB_X) & (CB_Y - 1));
+    const int cx = bb.c0[0] + (tid % CB_X);
+    const int cy = bb.c0[1] + (tid / CB_X) % CB_Y;
     const int cz = bb.c0[2] + tid / (CB_X * CB_Y);
     const bool valid = cx < gc.nx && cy < gc.ny && cz < gc.nz;
     // the brick in index coordinates: cells c0 .. c1 cover [c0, c1 + 1)
@@ -362,6 +446,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
     // this lane's cell faces in z (same expressions as the brick box)
     const float za = gc.z0 + (float)cz * gc.hz, zb = gc.z0 + (float)(cz + 1) * gc.hz;
     const float cxf = (float)cx, cyf = (float)cy, czf = (float)cz;
+    // largest |c_a| over the brick's cells, for the staged range margins
+    const float cmax[3] = {fmaxf(fabsf(blo[0]), fabsf(bhi[0])), fmaxf(fabsf(blo[1]), fabsf(bhi[1])),
+                           fmaxf(fabsf(blo[2]), fabsf(bhi[2]))};
+    // the brick's single z layer (CB_Z = 1): cell cz0 = blo[2]
+    static_assert(CB_Z == 1, "the staged z bounds assume one z layer per brick");
     T acc[8];
 #pragma unroll
     for (int o = 0; o < 8; ++o) acc[o] = T(0);
@@ -412,19 +501,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
                 }
                 const int sb = max(clamp_to_int(floor_t(tin)), 0) & ~(SEG - 1);
                 const SegOrigin o = seg_origin(vc.Qd, g.D, sb);
-                StagedRay e;
+                StagedRange er;
+                StagedWalk ew;
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const float inv = g.inv[a];
+                    const float m = __builtin_fmaf(
+                        4e-6f * (fabsf(vc.Q[a]) + cmax[a] + 1.0f), fabsf(inv), 1e-3f);
+                    er.inv[a] = inv;
+                    er.lo[a] = fminf(0.0f, inv) - m;
+                }
+                {
+                    // the z layer's bounds, as a cell of the layer would
+                    // compute them (cq = cz0 - Q_z in float)
+                    const float inv = g.inv[2];
+                    const float t0 = (blo[2] - vc.Q[2]) * inv, t1 = t0 + inv;
+                    const float m = __builtin_fmaf(
+                        4e-6f * (fabsf(vc.Q[2]) + cmax[2] + 1.0f), fabsf(inv), 1e-3f);
+                    er.zlo = fminf(t0, t1) - m;
+                    er.zhi = fmaxf(t0, t1) + m;
+                }
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    e.I[a] = (short)o.I[a];
-                    e.f[a] = o.f[a];
-                    e.Df[a] = (float)g.D[a];
-                    e.inv[a] = g.inv[a];
+                    ew.I[a] = (short)o.I[a];
+                    ew.f[a] = o.f[a];
+                    ew.Df[a] = (float)g.D[a];
                 }
                 // 32767 marks "no staged origin" (the plan bounds real
                 // sample indices below 32767 * SEG)
-                e.sq = (short)min(sb / SEG, 32767);
-                e.r = (float)rk[pix];
-                table[t] = e;
+                ew.sq = (short)min(sb / SEG, 32767);
+                ew.r = (float)rk[pix];
+                trange[t] = er;
+                twalk[t] = ew;
             }
         }
         __syncthreads();
@@ -451,6 +559,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
         j1 = min(j1, bj1);
         const float Qf[3] = {vc.Q[0], vc.Q[1], vc.Q[2]};
         const CellRange cr = cell_range(Qf, cxf, cyf, czf);
+        // 1 + 2 K_a of the staged margins (x, y)
+        const float kw[2] = {1.0f + 8e-6f * (fabsf(vc.Q[0]) + cmax[0] + 1.0f),
+                             1.0f + 8e-6f * (fabsf(vc.Q[1]) + cmax[1] + 1.0f)};
         // One flat loop over the cell's rectangle (nearly its exact
         // footprint): lanes with rectangles of different shapes then
         // diverge only in the total pixel count.
@@ -459,34 +570,49 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
         int i = i0, j = j0;
         if constexpr (sizeof(T) == 4) {
             if (staged) {
-                const StagedRay *row = table + (j0 - bj0) * bw - bi0;
+                // entries of pixel (i, j): pointers advanced along the
+                // rectangle (no per-visit multiplications)
+                const int e0 = (j0 - bj0) * bw + (i0 - bi0);
+                const StagedRange *pr = trange + e0;
+                const StagedWalk *pw = twalk + e0;
+                const int skip = bw - w;  // from a row's end to the next row's start
                 for (int q = 0; q < npix; ++q) {
-                    const StagedRay &e = row[i];
-                    const PixelRay *gray = raysk + (long long)j * nu + i;
+                    const RayRef ray{raysk, nu, i, j};
+                    visit_staged(acc, cr.cq, kw, *pr, pw, ray, vc.Qd, cx, cy, cz);
+                    ++pr;
+                    ++pw;
                     if (++i > i1) {
                         i = i0;
                         ++j;
-                        row += bw;
+                        pr += skip;
+                        pw += skip;
                     }
-                    visit_staged(acc, cr, e, gray, vc.Qd, cx, cy, cz);
                 }
                 continue;
             }
         }
         for (int q = 0; q < npix; ++q) {
+            const RayRef ray{raysk, nu, i, j};
             const long long pix = (long long)j * nu + i;
             if (++i > i1) {
                 i = i0;
                 ++j;
             }
-            visit_global<T>(acc, cr, raysk + pix, rk[pix], vc.Qd, cx, cy, cz);
+            visit_global<T>(acc, cr, ray, rk[pix], vc.Qd, cx, cy, cz);
         }
     }
     if (!valid) return;
     const long long ncell = (long long)(gc.nx + 1) * (gc.ny + 1) * (gc.nz + 1);
     const long long lin = (long long)(cx + 1) + (long long)(gc.nx + 1) * ((cy + 1) + (long long)(gc.ny + 1) * (cz + 1));
+    T out[8];
+    if constexpr (sizeof(T) == 4) {
+        moments_to_corners(acc, out);
+    } else {
 #pragma unroll
-    for (int o = 0; o < 8; ++o) cells[o * ncell + lin] = acc[o] * step;
+        for (int o = 0; o < 8; ++o) out[o] = acc[o];
+    }
+#pragma unroll
+    for (int o = 0; o < 8; ++o) cells[o * ncell + lin] = out[o] * step;
 }
 
 // Pass 2: out = sum of corner o of cell (v - o) over o in {0,1}^3,
