@@ -133,13 +133,13 @@ def parse():
                     help="views of the head scan the CPU oracle sample uses")
     ap.add_argument("--ops-reps", type=int, default=20,
                     help="timed launches per stand-alone operator (median reported)")
-    ap.add_argument("--serve-requests", type=int, default=12,
+    ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests in the served mixed stream (0 skips it)")
-    ap.add_argument("--serve-load", type=float, default=0.8,
+    ap.add_argument("--serve-load", type=float, default=1.5,
                     help="offered load of the served stream: arrival rate times the "
                          "mean one-at-a-time service time")
-    ap.add_argument("--lowdose", action="store_true",
-                    help="also run the 12-point low-dose quality sweep")
+    ap.add_argument("--no-lowdose", action="store_true",
+                    help="leave out the low-dose sweep (12 points plus the Eq. (2) runs)")
     ap.add_argument("--skip-schedules", action="store_true",
                     help="leave out the multigrid schedule comparison (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -280,7 +280,7 @@ def serving_benchmark(torch, cb, n_req, seed=5000, load=0.8):
     serial_makespan = done
     # the server in real time
     budget = int(0.6 * torch.cuda.mem_get_info()[0])
-    srv = Server(ex, hbm_budget=budget, max_active=8, iters_per_tick=1)
+    srv = Server(ex, hbm_budget=budget, max_active=4, iters_per_tick=1)
     srv.start()
     futs = []
     t0 = time.perf_counter()
@@ -314,8 +314,9 @@ def serving_benchmark(torch, cb, n_req, seed=5000, load=0.8):
         "serial_throughput_req_s": n_req / serial_makespan,
         "mean_alone_solve_s": mean_s,
         "peak_active": srv.peak_active,
-        "schedule": "20+20 iterations per request, 1 iteration per tick, up to 8 "
-                    "concurrent streams, admission by footprint",
+        "schedule": "20+20 iterations per request, 1 iteration per tick, up to 4 "
+                    "concurrent streams (one per hardware queue), least remaining work "
+                    "stepped first, admission by footprint in arrival order",
     }
 
 
@@ -389,30 +390,33 @@ def multigrid_schedules(torch, cb, plan, case, Y):
 
 def tiny_recon_times(torch, cb):
     """Seconds per reconstruction of the 64^3 / 16-view workload (10
-    iterations, beta and inner count from the oracle's rule on both sides):
-    the FP64 oracle on the host cores and the GPU solve."""
+    iterations): the FP64 oracle on the host cores and the GPU solve, each
+    with beta and the inner count from its own power iteration and rule."""
     import numpy as np
     import oracle
     from workloads import tiny_case
     case = tiny_case()
     g = case.geom
+    t0 = time.perf_counter()
     lam = oracle.power_lambda(g, 30)
     beta = oracle.beta_rule(g, case.mu, lam)
     k = oracle.default_inner(np.array([g.hx, g.hy, g.hz]), beta, case.eps)
-    t0 = time.perf_counter()
     oracle.fbs_solve(g, case.Y, case.mu, [10], beta=[beta], eps=case.eps, n_inner=[k])
     cpu_s = time.perf_counter() - t0
     plan = cb.Plan(g)
     Y = torch.as_tensor(case.Y, dtype=torch.float32, device="cuda")
-    p = cb.FbsParams(mu=case.mu, iters=(10,), beta=[beta], eps=case.eps, n_inner=[k])
-    cb.fbs_solve(plan, Y, p)
+    p = cb.FbsParams(mu=case.mu, iters=(10,), eps=case.eps)
+    _, rep = cb.fbs_solve(plan, Y, p)  # beta setup, cached by the plan
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(5):
         cb.fbs_solve(plan, Y, p)
     torch.cuda.synchronize()
     return {"cpu_oracle_s": cpu_s, "cpu_threads": oracle.threads(),
-            "gpu_s": (time.perf_counter() - t0) / 5, "n_inner": k}
+            "gpu_s": (time.perf_counter() - t0) / 5, "beta_oracle": beta,
+            "beta_gpu": rep.beta_used[0], "n_inner_oracle": k, "n_inner_gpu": rep.n_inner_used[0],
+            "note": "each side computes its own beta (30 power-iteration steps); the oracle "
+                    "time includes its power iteration, the GPU time is of warm solves"}
 
 
 def main():
@@ -567,8 +571,10 @@ def main():
         "paper_context": "77-130 s per reconstruction on a Tesla C1060 (different "
                          "hardware, phantom and iteration count; not a target)",
     }
-    if args.lowdose:
+    if not args.no_lowdose:
+        t = time.perf_counter()
         out["lowdose"] = lowdose_sweep(torch, cb)
+        log("low-dose sweep %.1f s" % (time.perf_counter() - t))
     if args.serve_requests > 0:
         t = time.perf_counter()
         out["serving"] = serving_benchmark(torch, cb, args.serve_requests, load=args.serve_load)

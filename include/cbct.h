@@ -260,7 +260,10 @@ int cbct_fbs_report_get(const cbct_fbs_state *s, cbct_fbs_report *rep);
 void cbct_fbs_free(cbct_fbs_state *s);
 
 /* Device bytes a solve of this geometry and schedule needs, including the
- * caller's Y and f arrays: the admission figure for schedulers. */
+ * caller's Y and f arrays: the admission figure for schedulers.  When some
+ * level's beta is to be estimated it includes the power iteration's scratch
+ * for the finest level (held during init; an upper bound when the plan has
+ * the estimate cached). */
 size_t cbct_fbs_footprint(const cbct_geom *g, const cbct_fbs_params *prm);
 
 /* Diagnostics: per-kernel device time.  cbct_kernel_timing(1) discards
@@ -289,6 +292,16 @@ int cbct_kernel_timing_read(int32_t kernel, int64_t *launches, double *total_ms)
  * events and writes TFLOP/s (2 flop per FMA) to *tflops_host.  Allocates
  * and frees a small output buffer; synchronises `stream`. */
 int cbct_probe_fma_rate(int32_t fp64, double *tflops_host, void *stream);
+
+/* Diagnostics: the tunable sizes of the float kernels, written to the host
+ * array out_host (at most n entries): [0] projector tile width and [1]
+ * height in pixels, [2] samples per chunk, [3] LDS box capacity in floats;
+ * [4..6] transpose brick in cells (x, y, z), [7] LDS table capacity in
+ * pixels.  A tile chunk whose box exceeds [3], or a brick whose footprint
+ * on the detector exceeds [7] pixels, reads global memory instead of LDS
+ * (same results).  Returns the number of entries written (8 when n >= 8),
+ * EINVAL for a NULL array or negative n.  No GPU work. */
+int cbct_kernel_config(int32_t *out_host, int32_t n);
 
 const char *cbct_strerror(int code);
 const char *cbct_last_error(void);

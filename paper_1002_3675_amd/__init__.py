@@ -435,6 +435,17 @@ def log_counts(counts, i0=None, flat=None, min_count: float = 1.0, out=None):
     return y
 
 
+def kernel_config() -> dict:
+    """Tunable sizes of the float kernels (cbct_kernel_config)."""
+    buf = (ctypes.c_int32 * 8)()
+    n = _native.lib().cbct_kernel_config(buf, 8)
+    if n < 0:
+        check(n, "cbct_kernel_config")
+    names = ("tile_u", "tile_v", "tile_chunk", "tile_lds_floats", "brick_x", "brick_y",
+             "brick_z", "table_pixels")
+    return {k: int(buf[i]) for i, k in enumerate(names)}
+
+
 def probe_fma_rate(fp64: bool = False) -> float:
     """Sustained non-packed FMA rate of the current device in TFLOP/s
     (float32, or float64 with fp64=True): the measured ALU ceiling."""

@@ -164,6 +164,15 @@ extern "C" int cbct_kernel_timing_read(int32_t kernel, int64_t *launches, double
     return CBCT_OK;
 }
 
+extern "C" int cbct_kernel_config(int32_t *out_host, int32_t n) {
+    if (!out_host || n < 0) return set_error(CBCT_EINVAL, "bad argument");
+    int32_t v[8];
+    projector_config(v);
+    cell_pass_config(v + 4);
+    for (int i = 0; i < n && i < 8; ++i) out_host[i] = v[i];
+    return n < 8 ? n : 8;
+}
+
 extern "C" int cbct_probe_fma_rate(int32_t fp64, double *tflops_host, void *stream) {
     if (!tflops_host) return set_error(CBCT_EINVAL, "tflops_host is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -893,6 +902,14 @@ extern "C" size_t cbct_fbs_footprint(const cbct_geom *g, const cbct_fbs_params *
                          (size_t)2 * ((g->nx + 63) / 64) * ((g->ny + 3) / 4) * g->nz);
     if (tol) np = std::max(np, (size_t)2 * DIFF_BLOCKS);
     b += sizeof(double) * (np + 8);
+    // beta from the power iteration: cbct_plan_lambda's scratch for the
+    // finest level, held during init (counted even when the plan has the
+    // estimate cached already)
+    bool estimate = false;
+    for (int l = 0; l < prm->n_levels; ++l) estimate |= !(prm->beta[l] > 0);
+    if (estimate)
+        b += sizeof(float) * (2 * nvox_of(*g) + nmeas_of(*g) + padded_of(*g)) +
+             bp_workspace_bytes(*g, sizeof(float)) + sizeof(double) * (4096 + 1);
     return b;
 }
 

@@ -730,6 +730,13 @@ BpLayout bp_layout(const cbct_geom &g, size_t elem) {
 
 size_t bp_workspace_bytes(const cbct_geom &g, size_t elem) { return bp_layout(g, elem).total; }
 
+void cell_pass_config(int32_t out[4]) {
+    out[0] = CB_X;
+    out[1] = CB_Y;
+    out[2] = CB_Z;
+    out[3] = TABLE;
+}
+
 hipError_t launch_bp_prepare(const cbct_plan &p, void *ws, size_t elem, hipStream_t s) {
     const BpLayout l = bp_layout(p.g, elem);
     char *base = (char *)ws;

@@ -112,6 +112,12 @@ hipError_t launch_eq2(const cbct_plan &p, const float *r, const float *f, double
                       float *out, hipStream_t s);
 hipError_t launch_count_samples(const cbct_plan &p, unsigned long long *count, hipStream_t s);
 
+// Tunable sizes of the float kernels (diagnostics): the projector's tile
+// width and height in pixels, samples per chunk and LDS box in floats; the
+// transpose's brick in cells (x, y, z) and LDS table in pixels.
+void projector_config(int32_t out[4]);
+void cell_pass_config(int32_t out[4]);
+
 size_t project_partials_count(const cbct_plan &p);
 size_t project_partials_count(const cbct_geom &g);
 size_t padded_count(const cbct_plan &p);

@@ -396,19 +396,30 @@ dim3 tile_grid(const cbct_plan &p) { return dim3((unsigned)tile_count(p.g)); }
 
 // Cells of margin around the corner rays' box: the samples of rays inside a
 // tile deviate from the corner rays' hull by at most t (1 - cos a) ~ t a^2/2,
-// with a the tile's angular half-diagonal and t the largest sample distance.
+// with a the tile's angular half-diagonal and t the largest sample distance
+// inside the bordered grid: at most the source's distance to the grid
+// centre (sad plus the grid's offset from the isocentre) plus half the
+// grid's diagonal.
 int tile_margin(const cbct_plan &p) {
     const cbct_geom &g = p.g;
     const double hd = sqrt(pow(0.5 * TILE_U * g.au, 2) + pow(0.5 * TILE_V * g.av, 2));
     const double a = hd / g.sdd;
-    const double tmax = g.sad + sqrt(pow(0.5 * (g.nx + 2) * g.hx, 2) +
-                                     pow(0.5 * (g.ny + 2) * g.hy, 2) +
-                                     pow(0.5 * (g.nz + 2) * g.hz, 2));
+    const double tmax = g.sad + sqrt(pow(g.x_off, 2) + pow(g.y_off, 2) + pow(g.z_off, 2)) +
+                        sqrt(pow(0.5 * (g.nx + 2) * g.hx, 2) +
+                             pow(0.5 * (g.ny + 2) * g.hy, 2) +
+                             pow(0.5 * (g.nz + 2) * g.hz, 2));
     const double bulge = tmax * 0.5 * a * a * 1.01 / std::min(g.hx, std::min(g.hy, g.hz));
     return std::max(1, (int)ceil(bulge + 1e-3));
 }
 
 }  // namespace
+
+void projector_config(int32_t out[4]) {
+    out[0] = TILE_U;
+    out[1] = TILE_V;
+    out[2] = TILE_CH;
+    out[3] = TILE_LDS;
+}
 
 // Partial sums written by a float projection (one per workgroup of the
 // tile grid); the double projector takes no partials.

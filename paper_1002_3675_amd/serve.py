@@ -65,15 +65,21 @@ class _Slot:
 
 
 class Server:
-    """Admission by footprint, round-robin stepping, completion polling.
+    """Admission by footprint, stepping by least remaining work, completion
+    polling.
 
     hbm_budget: device bytes the admitted requests may hold together.
-    max_active: execution slots (requests advanced concurrently).
+    max_active: execution slots (requests advanced concurrently); the
+    default 4 matches the hardware queues a process gets, so each active
+    request's stream has a queue of its own.
     iters_per_tick: outer iterations enqueued per request per tick.
+    Each tick offers work to the active requests in order of the work they
+    have left (executor.remaining, ties by admission), so a small request
+    admitted behind large ones has its kernels queued first.
     Call start() for a background scheduler thread, or tick() yourself.
     """
 
-    def __init__(self, executor, hbm_budget: int, max_active: int = 8,
+    def __init__(self, executor, hbm_budget: int, max_active: int = 4,
                  iters_per_tick: int = 1, clock: Callable[[], float] = time.perf_counter):
         if hbm_budget <= 0 or max_active <= 0 or iters_per_tick <= 0:
             raise ValueError("budget, slots and iterations per tick must be positive")
@@ -123,7 +129,11 @@ class Server:
     def tick(self) -> bool:
         """One scheduling round; returns True if it did any work."""
         worked = self._admit()
-        for s in list(self._active):
+        rem = getattr(self.ex, "remaining", None)
+        order = list(self._active)
+        if rem is not None:
+            order.sort(key=lambda s: rem(s.handle))  # stable: ties keep admission order
+        for s in order:
             try:
                 if not self.ex.finished(s.handle):
                     worked |= bool(self.ex.step(s.handle, self.iters_per_tick))
@@ -264,11 +274,23 @@ class GpuExecutor:
             Y = Y.contiguous()
             f = torch.zeros(plan.geom.vol_shape, dtype=torch.float32, device=self.device)
         st = self.cb.FbsState(plan, Y, f, req.params, stream=stream)
+        g = plan.geom
+        nvox = float(g.nx * g.ny * g.nz)
+        iters = list(req.params.iters)
+        # level l (coarse first) has about 8^-(levels - 1 - l) of the voxels
+        per_iter = [nvox / 8.0 ** (len(iters) - 1 - l) for l in range(len(iters))]
         return {"st": st, "stream": stream, "Y": Y, "f": f, "events": collections.deque(),
-                "done_event": None}
+                "done_event": None, "sched": [it for it in iters], "per_iter": per_iter,
+                "work_left": sum(n * w for n, w in zip(iters, per_iter))}
 
     def finished(self, h) -> bool:
         return h["st"].finished
+
+    def remaining(self, h) -> float:
+        """Work left, in fine-level iteration equivalents: iterations not yet
+        enqueued, a level's weighted by its voxel count over the finest's,
+        times the finest level's voxel count (so requests compare)."""
+        return h["work_left"]
 
     def step(self, h, n) -> bool:
         ev = h["events"]
@@ -281,6 +303,14 @@ class GpuExecutor:
             e = self.torch.cuda.Event()
             e.record(h["stream"])
         ev.append(e)
+        # the schedule as enqueued so far (a tolerance stop may end a level
+        # earlier; the figure only orders the requests)
+        left = n
+        for l, it in enumerate(h["sched"]):
+            take = min(it, left)
+            h["sched"][l] -= take
+            left -= take
+        h["work_left"] = sum(i * w for i, w in zip(h["sched"], h["per_iter"]))
         if h["st"].finished:
             h["done_event"] = e
         return True

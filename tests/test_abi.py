@@ -128,6 +128,20 @@ def test_footprint_is_host_arithmetic():
     assert two > one
 
 
+def test_footprint_counts_the_power_iteration_when_beta_is_estimated():
+    import paper_1002_3675_amd as cb
+    from workloads import head_geometry
+    g = head_geometry(40)
+    given = cb.footprint(g, cb.FbsParams(iters=(20, 20), beta=[500.0, 500.0]))
+    est = cb.footprint(g, cb.FbsParams(iters=(20, 20)))
+    partly = cb.footprint(g, cb.FbsParams(iters=(20, 20), beta=[500.0, 0.0]))
+    # the fine level's power iteration: two volumes, a projection stack, the
+    # bordered volume and the cell workspace
+    extra = 4 * (2 * g.n_vox + g.n_meas + 514 * 514 * 72) + 4 * 8 * 513 * 513 * 71
+    assert est - given >= extra
+    assert partly == est
+
+
 def test_solver_parameters_are_checked_on_the_host():
     """Levels, tolerance and shifts are validated before any device call:
     footprint() returns 0 for what init would refuse."""

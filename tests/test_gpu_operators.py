@@ -189,17 +189,50 @@ def test_diff_size_transpose_matches_oracle():
     assert rel_l2(f, oracle.backproject(g, y)) <= TOL
 
 
-# Geometries that force each operator's fallback path.
-# P^T: 2 mm voxels seen through 0.2 mm pixels at magnification 1.5, so an
-# 8x8x4-cell brick covers ~120 x 60 detector pixels, far beyond the LDS ray
-# table (640 pixels): every brick reads its rays from the global ray table.
+# Geometries that force each operator's fallback path (the sizes they
+# exceed come from the library, cbct_kernel_config; the lower bounds below
+# are checked on the host by fallback_margins and by
+# tests/test_kernel_config.py).
+# P^T: 2 mm voxels seen through 0.2 mm pixels at magnification ~1.4, so a
+# full brick's footprint is hundreds of pixels wide and more than ten rows
+# tall, far beyond the LDS table: every full brick reads its rays from the
+# global ray table.
 PT_FALLBACK = Geometry(16, 16, 16, 2.0, 2.0, 2.0, 256, 256, 0.2, 0.2, 300.0, 450.0, 3,
                        angles=(0.3, 1.9, 4.0))
-# P: 8 mm pixels over 1 mm voxels, so the rays of a 32 x 8 pixel tile fan
-# over ~170 x 40 voxels and no 16-sample chunk's box fits the 16 KB of LDS:
-# every tap is read from the bordered volume in global memory.
+# P: 8 mm pixels over 1 mm voxels, so the rays of one tile fan over the
+# whole grid cross-section and no chunk's box fits the LDS box: every tap is
+# read from the bordered volume in global memory.
 P_FALLBACK = Geometry(48, 48, 48, 1.0, 1.0, 1.0, 24, 16, 8.0, 8.0, 300.0, 450.0, 3,
                       angles=(0.2, 2.2, 4.5))
+
+
+def fallback_margins(cfg):
+    """Host lower bounds of (full-brick footprint in pixels over the LDS
+    table, projector chunk box in cells over the LDS box) for PT_FALLBACK
+    and P_FALLBACK; both must exceed 1 for the fallbacks to be taken."""
+    g = PT_FALLBACK
+    # nearest and farthest points of the grid from the source
+    half = 0.5 * math.sqrt((g.nx * g.hx) ** 2 + (g.ny * g.hy) ** 2)
+    m_min = g.sdd / (g.sad + half)
+    # a brick of bx x by cells (full bricks: smaller than the grid) spans at
+    # least min(bx hx, by hy) perpendicular to any ray in xy, and bz hz in z
+    bx, by, bz = cfg["brick_x"], cfg["brick_y"], cfg["brick_z"]
+    cols = min(bx * g.hx, by * g.hy) * m_min / g.au
+    rows = bz * g.hz * m_min / g.av
+    pt = (math.floor(cols) * math.floor(rows)) / cfg["table_pixels"]
+    g = P_FALLBACK
+    # a tile's rays span tile * pitch * d / sdd at distance d from the
+    # source; inside the grid d >= sad - half, and the box is clipped to
+    # the bordered grid; a chunk advances chunk * step along the ray, at
+    # least chunk * step / sqrt(3) along its dominant axis
+    half = 0.5 * math.sqrt((g.nx * g.hx) ** 2 + (g.ny * g.hy) ** 2 + (g.nz * g.hz) ** 2)
+    d = g.sad - half
+    span_u = min(cfg["tile_u"] * g.au * d / g.sdd / g.hx, g.nx + 2)
+    span_v = min(cfg["tile_v"] * g.av * d / g.sdd / g.hz, g.nz + 2)
+    step = 0.5 * min(g.hx, g.hy, g.hz)
+    depth = cfg["tile_chunk"] * step / math.sqrt(3.0) / max(g.hx, g.hy)
+    p = (math.floor(span_u) * math.floor(span_v) * math.floor(depth)) / cfg["tile_lds_floats"]
+    return pt, p
 
 
 @pytest.mark.parametrize("name,g", [("pt_fallback", PT_FALLBACK), ("p_fallback", P_FALLBACK)])

@@ -169,3 +169,40 @@ def test_scheduler_fault_fails_every_request_instead_of_hanging():
     with pytest.raises(RuntimeError, match="server loop failed"):
         srv.submit(_req(10, 3)).result(timeout=1)
     srv._thread.join(timeout=5)
+
+
+class RankedExecutor(FakeExecutor):
+    """A fake executor that also reports the work left and logs step order."""
+
+    def __init__(self):
+        super().__init__()
+        self.order = []
+
+    def remaining(self, h):
+        return h["req"].params["iters"] - h["done"]
+
+    def step(self, h, n):
+        self.order.append(h["req"].id)
+        return super().step(h, n)
+
+
+def test_requests_with_least_work_left_are_stepped_first():
+    ex = RankedExecutor()
+    srv = Server(ex, hbm_budget=1000, max_active=4)
+    futs = [srv.submit(_req(10, it, rid)) for rid, it in ((0, 9), (1, 2), (2, 5), (3, 1))]
+    srv.tick()
+    # one tick: all four admitted, stepped in order of work left
+    assert ex.order == [3, 1, 2, 0]
+    srv.run_until_idle(timeout=10)
+    assert [f.result().f for f in futs] == ["f0", "f1", "f2", "f3"]
+    # ties keep admission order
+    ex2 = RankedExecutor()
+    srv2 = Server(ex2, hbm_budget=1000, max_active=4)
+    for rid in range(3):
+        srv2.submit(_req(10, 4, rid))
+    srv2.tick()
+    assert ex2.order == [0, 1, 2]
+
+
+def test_default_slots_match_the_hardware_queues():
+    assert Server(FakeExecutor(), hbm_budget=10).max_active == 4
