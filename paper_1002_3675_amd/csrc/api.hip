@@ -383,6 +383,11 @@ extern "C" int cbct_plan_create(const cbct_geom *gin, cbct_plan **out) {
 extern "C" void cbct_plan_destroy(cbct_plan *p) {
     if (!p) return;
     if (p->coarse) cbct_plan_destroy(p->coarse);
+    if (p->bp_ready) {
+        (void)hipEventSynchronize(p->bp_ready);
+        (void)hipEventDestroy(p->bp_ready);
+    }
+    if (p->bp_geom) (void)hipFree(p->bp_geom);
     if (p->d_views) (void)hipFree(p->d_views);
     delete p;
 }
@@ -421,18 +426,48 @@ int project_impl(const cbct_plan *p, const T *f, const T *Y, T *out, double *sum
     return rc;
 }
 
+// The plan's transpose geometry tables, prepared on the first call (on
+// stream s) and afterwards only waited for on s.
+int plan_bp_geometry(const cbct_plan *p, hipStream_t s, const void **out) {
+    std::lock_guard<std::mutex> lk(p->bp_mu);
+    if (!p->bp_geom) {
+        void *g = nullptr;
+        int rc = check_hip(hipMalloc(&g, bp_geom_bytes(p->g)), "plan transpose tables");
+        if (rc) return rc;
+        hipEvent_t ev = nullptr;
+        rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_bp_prepare(*p, g, s); }),
+                       "ray table");
+        if (!rc) rc = check_hip(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+        if (!rc) rc = check_hip(hipEventRecord(ev, s), "event record");
+        if (rc) {
+            if (ev) (void)hipEventDestroy(ev);
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(g);
+            return rc;
+        }
+        p->bp_geom = g;
+        p->bp_ready = ev;
+    } else {
+        int rc = check_hip(hipStreamWaitEvent(s, p->bp_ready, 0), "wait for the plan tables");
+        if (rc) return rc;
+    }
+    *out = p->bp_geom;
+    return CBCT_OK;
+}
+
 template <typename T>
 int backproject_impl(const cbct_plan *p, const T *y, const T *f, double tau, T *out,
                      hipStream_t s) {
     if (!p || !y || !out) return set_error(CBCT_EINVAL, "NULL argument");
-    Scratch ws(s);
-    int rc = check_hip(ws.alloc(bp_workspace_bytes(p->g, sizeof(T))), "scratch (transpose workspace)");
+    const void *geom = nullptr;
+    int rc = plan_bp_geometry(p, s, &geom);
     if (rc) return rc;
-    rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_bp_prepare(*p, ws.get(), sizeof(T), s); }), "ray table");
+    Scratch cells(s);
+    rc = check_hip(cells.alloc(bp_cells_bytes(p->g, sizeof(T))), "scratch (transpose cell sums)");
     if (rc) return rc;
-    rc = check_hip(timed(CBCT_KERNEL_CELLS, s, [&] { return launch_backproject_cells<T>(*p, y, ws.get(), s); }), "cell kernel");
+    rc = check_hip(timed(CBCT_KERNEL_CELLS, s, [&] { return launch_backproject_cells<T>(*p, y, cells.get(), geom, s); }), "cell kernel");
     if (rc) return rc;
-    return check_hip(timed(CBCT_KERNEL_GATHER, s, [&] { return launch_gather_cells<T>(*p, ws.get(), f, tau, out, s); }), "gather kernel");
+    return check_hip(timed(CBCT_KERNEL_GATHER, s, [&] { return launch_gather_cells<T>(*p, cells.get(), f, tau, out, s); }), "gather kernel");
 }
 
 }  // namespace
@@ -670,7 +705,7 @@ extern "C" int cbct_plan_lambda(const cbct_plan *p, int32_t n_iter, double *lamb
         if (rc) return rc;
         rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_fill(x.as<float>(), nvox, (float)(1.0 / sqrt((double)nvox)), s); }),
                        "fill");
-        if (!rc) rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_bp_prepare(*p, cells.get(), sizeof(float), s); }), "ray table");
+        if (!rc) rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_bp_prepare(*p, bp_geom_in(cells.get(), p->g, sizeof(float)), s); }), "ray table");
         for (int it = 0; !rc && it < n_iter; ++it) {
             rc = check_hip(timed(CBCT_KERNEL_PAD, s, [&] { return launch_pad<float>(*p, x.as<float>(), pad.as<float>(), s); }), "pad");
             if (!rc)
@@ -678,8 +713,8 @@ extern "C" int cbct_plan_lambda(const cbct_plan *p, int32_t n_iter, double *lamb
                                                      nullptr, s); }),
                                "project");
             if (!rc)
-                rc = check_hip(timed(CBCT_KERNEL_CELLS, s, [&] { return launch_backproject_cells<float>(*p, y.as<float>(),
-                                                               cells.get(), s); }),
+                rc = check_hip(timed(CBCT_KERNEL_CELLS, s, [&] { return launch_backproject_cells<float>(*p, y.as<float>(), cells.get(),
+                                                               bp_geom_in(cells.get(), p->g, sizeof(float)), s); }),
                                "cells");
             if (!rc)
                 rc = check_hip(timed(CBCT_KERNEL_GATHER, s, [&] { return launch_gather_cells<float>(*p, cells.get(), nullptr, 0.0,
@@ -858,7 +893,7 @@ int fbs_iteration(cbct_fbs_state *st, Level &L, hipStream_t s, bool have_residua
         // the paper's Eq. (2) as printed, fused with the update
         if (!rc) rc = check_hip(timed(CBCT_KERNEL_EQ2, s, [&] { return launch_eq2(p, L.r, L.f, L.tau, L.g, s); }), "eq2");
     } else {
-        if (!rc) rc = check_hip(timed(CBCT_KERNEL_CELLS, s, [&] { return launch_backproject_cells<float>(p, L.r, L.cells, s); }), "cells");
+        if (!rc) rc = check_hip(timed(CBCT_KERNEL_CELLS, s, [&] { return launch_backproject_cells<float>(p, L.r, L.cells, bp_geom_in(L.cells, p.g, sizeof(float)), s); }), "cells");
         if (!rc) rc = check_hip(timed(CBCT_KERNEL_GATHER, s, [&] { return launch_gather_cells<float>(p, L.cells, L.f, L.tau, L.g, s); }), "gather");
     }
     // Steps 2 and 3 (minimise, correct), from z0 = f
@@ -971,7 +1006,7 @@ extern "C" int cbct_fbs_init(const cbct_plan *fine, const float *Y, float *f,
             if (!rc && tol) rc = alloc_owned(st.get(), (void **)&L.fprev, sizeof(float) * L.nvox, s);
             if (!rc && prm->gradient == 0) {
                 rc = alloc_owned(st.get(), (void **)&L.cells, bp_workspace_bytes(p.g, sizeof(float)), s);
-                if (!rc) rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_bp_prepare(p, L.cells, sizeof(float), s); }), "ray table");
+                if (!rc) rc = check_hip(timed(CBCT_KERNEL_OTHER, s, [&] { return launch_bp_prepare(p, bp_geom_in(L.cells, p.g, sizeof(float)), s); }), "ray table");
             }
         }
         // data and start of each coarser level from the next finer one

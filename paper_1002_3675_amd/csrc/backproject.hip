@@ -713,22 +713,35 @@ dim3 brick_grid(const cbct_geom &g) {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-struct BpLayout {
-    size_t rays, rects, total;  // byte offsets; the cell sums start at 0
+// Geometry tables of the transpose: the ray table at offset 0, then the
+// brick rectangles.
+struct GeomLayout {
+    size_t rects, total;  // byte offsets
 };
 
-BpLayout bp_layout(const cbct_geom &g, size_t elem) {
+GeomLayout geom_layout(const cbct_geom &g) {
     const dim3 b = brick_grid(g);
-    BpLayout l;
-    l.rays = align256(elem * 8 * (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1));
-    l.rects = l.rays + align256(sizeof(PixelRay) * (size_t)g.n_views * g.nu * g.nv);
+    GeomLayout l;
+    l.rects = align256(sizeof(PixelRay) * (size_t)g.n_views * g.nu * g.nv);
     l.total = l.rects + sizeof(int4) * (size_t)b.x * b.y * b.z * g.n_views;
     return l;
 }
 
 }  // namespace
 
-size_t bp_workspace_bytes(const cbct_geom &g, size_t elem) { return bp_layout(g, elem).total; }
+size_t bp_cells_bytes(const cbct_geom &g, size_t elem) {
+    return align256(elem * 8 * (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1));
+}
+
+size_t bp_geom_bytes(const cbct_geom &g) { return geom_layout(g).total; }
+
+size_t bp_workspace_bytes(const cbct_geom &g, size_t elem) {
+    return bp_cells_bytes(g, elem) + bp_geom_bytes(g);
+}
+
+void *bp_geom_in(void *ws, const cbct_geom &g, size_t elem) {
+    return (char *)ws + bp_cells_bytes(g, elem);
+}
 
 void cell_pass_config(int32_t out[4]) {
     out[0] = CB_X;
@@ -737,11 +750,11 @@ void cell_pass_config(int32_t out[4]) {
     out[3] = TABLE;
 }
 
-hipError_t launch_bp_prepare(const cbct_plan &p, void *ws, size_t elem, hipStream_t s) {
-    const BpLayout l = bp_layout(p.g, elem);
-    char *base = (char *)ws;
+hipError_t launch_bp_prepare(const cbct_plan &p, void *geom, hipStream_t s) {
+    const GeomLayout l = geom_layout(p.g);
+    char *base = (char *)geom;
     hipLaunchKernelGGL(k_rays, dim3((p.g.nu + 63) / 64, (p.g.nv + 3) / 4, p.g.n_views), dim3(256),
-                       0, s, p.d_views, p.det, p.g.nu, p.g.nv, (PixelRay *)(base + l.rays));
+                       0, s, p.d_views, p.det, p.g.nu, p.g.nv, (PixelRay *)base);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 b = brick_grid(p.g);
@@ -753,13 +766,14 @@ hipError_t launch_bp_prepare(const cbct_plan &p, void *ws, size_t elem, hipStrea
 }
 
 template <typename T>
-hipError_t launch_backproject_cells(const cbct_plan &p, const T *r, void *ws, hipStream_t s) {
-    const BpLayout l = bp_layout(p.g, sizeof(T));
-    char *base = (char *)ws;
+hipError_t launch_backproject_cells(const cbct_plan &p, const T *r, void *cells,
+                                    const void *geom, hipStream_t s) {
+    const GeomLayout l = geom_layout(p.g);
+    const char *base = (const char *)geom;
     const dim3 b = brick_grid(p.g);
     hipLaunchKernelGGL(k_cells<T>, dim3(b.x * b.y * b.z), dim3(256), 0, s, p.d_views, p.det, p.grid,
-                       p.g.nu, p.g.nv, p.g.n_views, (const PixelRay *)(base + l.rays),
-                       (const int4 *)(base + l.rects), r, (T *)ws, (T)p.g.step);
+                       p.g.nu, p.g.nv, p.g.n_views, (const PixelRay *)base,
+                       (const int4 *)(base + l.rects), r, (T *)cells, (T)p.g.step);
     return hipGetLastError();
 }
 
@@ -782,9 +796,9 @@ hipError_t launch_eq2(const cbct_plan &p, const float *r, const float *f, double
 }
 
 template hipError_t launch_backproject_cells<float>(const cbct_plan &, const float *, void *,
-                                                    hipStream_t);
+                                                    const void *, hipStream_t);
 template hipError_t launch_backproject_cells<double>(const cbct_plan &, const double *, void *,
-                                                     hipStream_t);
+                                                     const void *, hipStream_t);
 template hipError_t launch_gather_cells<float>(const cbct_plan &, const void *, const float *,
                                                double, float *, hipStream_t);
 template hipError_t launch_gather_cells<double>(const cbct_plan &, const void *,

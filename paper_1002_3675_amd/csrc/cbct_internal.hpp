@@ -75,6 +75,12 @@ struct cbct_plan {
     // next coarser multigrid level, created on first use
     mutable std::mutex coarse_mu;
     mutable cbct_plan *coarse = nullptr;
+    // the transpose's geometry tables for the stand-alone operators,
+    // prepared on first use (on that call's stream; bp_ready marks their
+    // completion for other streams) and freed with the plan
+    mutable std::mutex bp_mu;
+    mutable void *bp_geom = nullptr;
+    mutable hipEvent_t bp_ready = nullptr;
 };
 
 namespace cbct {
@@ -95,14 +101,20 @@ hipError_t launch_pad(const cbct_plan &p, const T *f, T *fpad, hipStream_t s);
 template <typename T>
 hipError_t launch_project(const cbct_plan &p, const T *fpad, const T *Y, T *out,
                           double *partials, hipStream_t s);
-// The transpose works in a workspace of bp_workspace_bytes(p, sizeof(T))
-// bytes: the cell corner sums (at offset 0), then a per-pixel ray table and
-// per-brick pixel rectangles, which depend on the geometry only and are
-// filled by launch_bp_prepare before the first launch_backproject_cells.
+// The transpose needs the cell corner sums (bp_cells_bytes, written by
+// launch_backproject_cells, read by launch_gather_cells) and the geometry
+// tables (bp_geom_bytes: a per-pixel ray table and per-brick pixel
+// rectangles), which depend on the plan only and are filled by
+// launch_bp_prepare.  A combined workspace of bp_workspace_bytes holds the
+// corner sums at offset 0 and the geometry tables at bp_geom_in.
+size_t bp_cells_bytes(const cbct_geom &g, size_t elem_size);
+size_t bp_geom_bytes(const cbct_geom &g);
 size_t bp_workspace_bytes(const cbct_geom &g, size_t elem_size);
-hipError_t launch_bp_prepare(const cbct_plan &p, void *ws, size_t elem_size, hipStream_t s);
+void *bp_geom_in(void *ws, const cbct_geom &g, size_t elem_size);
+hipError_t launch_bp_prepare(const cbct_plan &p, void *geom, hipStream_t s);
 template <typename T>
-hipError_t launch_backproject_cells(const cbct_plan &p, const T *r, void *ws, hipStream_t s);
+hipError_t launch_backproject_cells(const cbct_plan &p, const T *r, void *cells,
+                                    const void *geom, hipStream_t s);
 template <typename T>
 hipError_t launch_gather_cells(const cbct_plan &p, const void *ws, const T *f, double tau,
                                T *out, hipStream_t s);

@@ -18,16 +18,21 @@ namespace {
 
 constexpr int TV_BX = 64;
 constexpr int TV_BY = 4;
-constexpr int ST_X = 32, ST_Y = 8, ST_Z = 16;  // sweep tile and z chunk
+constexpr int ST_X = 32, ST_Y = 8;  // sweep tile
+constexpr int ST_Z = 16;            // longest z chunk
+// A sweep should put at least this many workgroups in flight (8 per CU):
+// grids with few 32 x 8 columns get shorter z chunks.
+constexpr int SWEEP_MIN_GROUPS = 2048;
 
 struct TvArgs {
     int nx, ny, nz;
     float ihx, ihy, ihz;  // 1/h
     float eps2;
+    int zc;  // z chunk of the sweep (planes)
 };
 
 // Tiles of a sweep: 32 x 8 columns of the xy plane (x-fastest, then y) in
-// chunks of ST_Z planes, chunk-major in launch order.  Within a chunk each
+// chunks of a.zc planes, chunk-major in launch order.  Within a chunk each
 // XCD takes one contiguous range of columns (xcd_tile), so neighbouring
 // tiles share their halo lines in one L2.  The remap stays inside a chunk:
 // over the whole grid it would hand the last, shorter chunks to one XCD.
@@ -44,8 +49,8 @@ __device__ __forceinline__ SweepTile sweep_tile(const TvArgs &a, int b) {
     SweepTile t;
     t.i0 = bx * ST_X;
     t.j0 = by * ST_Y;
-    t.k0 = bz * ST_Z;
-    t.k1 = min(t.k0 + ST_Z, a.nz);
+    t.k0 = bz * a.zc;
+    t.k1 = min(t.k0 + a.zc, a.nz);
     return t;
 }
 
@@ -189,6 +194,14 @@ TvArgs args_of(const GridConst &gc, double eps) {
     a.ihy = (float)(1.0 / (double)gc.hy);
     a.ihz = (float)(1.0 / (double)gc.hz);
     a.eps2 = (float)(eps * eps);
+    // z chunk: up to ST_Z planes, shorter when the columns alone would
+    // leave the CUs short of workgroups (each chunk re-reads the plane
+    // below it and one above: (zc + 2) / zc of the z reads)
+    const int cols = ((gc.nx + ST_X - 1) / ST_X) * ((gc.ny + ST_Y - 1) / ST_Y);
+    const int want = (SWEEP_MIN_GROUPS + cols - 1) / cols;  // chunks wanted
+    int zc = (gc.nz + want - 1) / want;
+    zc = zc < 2 ? 2 : (zc > ST_Z ? ST_Z : zc);
+    a.zc = zc;
     return a;
 }
 
@@ -200,10 +213,11 @@ dim3 tv_grid(const GridConst &gc) {
 
 hipError_t launch_tv_sweep(const GridConst &gc, const float *z, const float *g, float *out,
                            float beta, float eps, float step, int nonneg, hipStream_t s) {
+    const TvArgs a = args_of(gc, eps);
     const int grid = ((gc.nx + ST_X - 1) / ST_X) * ((gc.ny + ST_Y - 1) / ST_Y) *
-                     ((gc.nz + ST_Z - 1) / ST_Z);
-    hipLaunchKernelGGL(k_tv_sweep, dim3(grid), dim3(256), 0, s, args_of(gc, eps), z, g,
-                       out, beta, step, nonneg);
+                     ((gc.nz + a.zc - 1) / a.zc);
+    hipLaunchKernelGGL(k_tv_sweep, dim3(grid), dim3(256), 0, s, a, z, g, out, beta, step,
+                       nonneg);
     return hipGetLastError();
 }
 

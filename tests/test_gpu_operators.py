@@ -266,3 +266,25 @@ def test_fma_rate_probe_is_plausible():
     f64 = cb.probe_fma_rate(True)
     assert 1.0 < f32 <= 157.3 * 1.05, f32
     assert 1.0 < f64 <= 78.6 * 1.05, f64
+
+
+def test_transpose_tables_are_prepared_once_and_shared_by_streams():
+    """The plan prepares the transpose's geometry tables on its first call
+    (here on a side stream) and every later call, on any stream, waits for
+    them: results are bitwise those of a fresh plan."""
+    torch = require_gpu()
+    g = RAGGED
+    rng = np.random.default_rng(21)
+    y = to_dev(rng.uniform(-1.0, 4.0, g.proj_shape))
+    want = _plan(g).backproject(y)
+    plan = _plan(g)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s1):
+        a = plan.backproject(y)
+    with torch.cuda.stream(s2):
+        b = plan.backproject(y)
+    torch.cuda.synchronize()
+    assert torch.equal(a, want) and torch.equal(b, want)
+    assert torch.equal(plan.backproject(y), want)
