@@ -40,13 +40,10 @@ constexpr int TABLE = CBCT_CELL_TABLE;         // pixels staged per view (60 B e
 constexpr int G_BX = 64, G_BY = 4;            // pass-2 block
 
 // Ray table entry per pixel and view (prepared once): the ray increment D
-// in double (segment origins) and the reciprocals of its float rounding
-// (range estimates; 1e30 stands for the reciprocal of an exactly zero
-// component).
+// in double (segment origins).  Readers form the reciprocals of its float
+// rounding for the range estimates themselves (ray_inv).  24 bytes.
 struct PixelRay {
     double D[3];
-    float inv[3];
-    float pad;
 };
 
 // LDS entry per footprint pixel of the current view, in two parts.
@@ -88,6 +85,13 @@ struct StagedWalk {
 
 __device__ __forceinline__ float inv_or_huge(float d) {
     return d != 0.0f ? __builtin_amdgcn_rcpf(d) : 1e30f;
+}
+
+// Reciprocals of the float rounding of a ray's increment (1e30 stands for
+// the reciprocal of an exactly zero component).
+__device__ __forceinline__ void ray_inv(const PixelRay &g, float inv[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) inv[a] = inv_or_huge((float)g.D[a]);
 }
 
 // Per-lane, per-view constants of the candidate range of cell c: along
@@ -306,16 +310,10 @@ __global__ __launch_bounds__(256) void k_rays(const ViewConst *__restrict__ view
     if (i >= nu || j >= nv) return;
     double Q[3], D[3];
     ray_setup(views[k], dc, i, j, Q, D);
-    float Df[3];
-    to_float3(D, Df);
     PixelRay e;
     e.D[0] = D[0];
     e.D[1] = D[1];
     e.D[2] = D[2];
-    e.inv[0] = inv_or_huge(Df[0]);
-    e.inv[1] = inv_or_huge(Df[1]);
-    e.inv[2] = inv_or_huge(Df[2]);
-    e.pad = 0.0f;
     rays[((long long)k * nv + j) * nu + i] = e;
 }
 
@@ -400,10 +398,12 @@ template <typename T>
 __device__ __forceinline__ void visit_global(T acc[8], const CellRange &cr, const RayRef &ray,
                                              T rv, const double Qd[3], int cx, int cy, int cz) {
     const PixelRay *gray = ray.get();
-    const float inv[3] = {gray->inv[0], gray->inv[1], gray->inv[2]};
+    const PixelRay g = *gray;
+    float inv[3];
+    ray_inv(g, inv);
     int n0, n1;
     if (!candidates_inv(cr, inv, n0, n1)) return;
-    const double D[3] = {gray->D[0], gray->D[1], gray->D[2]};
+    const double D[3] = {g.D[0], g.D[1], g.D[2]};
     if constexpr (sizeof(T) == 4) {
         const int ns = n0 & ~(SEG - 1);
         float Df[3];
@@ -490,13 +490,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
                 const int col = t - row * bw;
                 const long long pix = (long long)(bj0 + row) * nu + (bi0 + col);
                 const PixelRay g = raysk[pix];
+                float ginv[3];
+                ray_inv(g, ginv);
                 // first sample of the ray in the brick (a float estimate:
                 // it only picks which segment origin to prepare)
                 float tin = -3.0e38f;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const float t0 = (blo[a] - vc.Q[a]) * g.inv[a];
-                    const float t1 = (bhi[a] - vc.Q[a]) * g.inv[a];
+                    const float t0 = (blo[a] - vc.Q[a]) * ginv[a];
+                    const float t1 = (bhi[a] - vc.Q[a]) * ginv[a];
                     tin = fmaxf(tin, fminf(t0, t1));
                 }
                 const int sb = max(clamp_to_int(floor_t(tin)), 0) & ~(SEG - 1);
@@ -505,7 +507,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
                 StagedWalk ew;
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
-                    const float inv = g.inv[a];
+                    const float inv = ginv[a];
                     const float m = __builtin_fmaf(
                         4e-6f * (fabsf(vc.Q[a]) + cmax[a] + 1.0f), fabsf(inv), 1e-3f);
                     er.inv[a] = inv;
@@ -514,7 +516,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
                 {
                     // the z layer's bounds, as a cell of the layer would
                     // compute them (cq = cz0 - Q_z in float)
-                    const float inv = g.inv[2];
+                    const float inv = ginv[2];
                     const float t0 = (blo[2] - vc.Q[2]) * inv, t1 = t0 + inv;
                     const float m = __builtin_fmaf(
                         4e-6f * (fabsf(vc.Q[2]) + cmax[2] + 1.0f), fabsf(inv), 1e-3f);
