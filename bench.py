@@ -140,6 +140,8 @@ def parse():
                          "mean one-at-a-time service time")
     ap.add_argument("--no-lowdose", action="store_true",
                     help="leave out the low-dose sweep (12 points plus the Eq. (2) runs)")
+    ap.add_argument("--converge", action="store_true",
+                    help="also run the tiny and head workloads to convergence (about a minute)")
     ap.add_argument("--skip-schedules", action="store_true",
                     help="leave out the multigrid schedule comparison (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -388,6 +390,45 @@ def multigrid_schedules(torch, cb, plan, case, Y):
     return rows
 
 
+def convergence_study(torch, cb, plan, case, Y):
+    """How far the fixed iteration counts stop from the minimiser: the tiny
+    workload (10 iterations) and the head workload (20 + 20) against solves
+    run to a relative change below 1e-6 (tiny) or 1e-5 (head, three levels),
+    with the final energy E and the relative L2 error to the voxelised
+    phantom over the field of view."""
+    import numpy as np
+    from workloads import fov_mask, tiny_case, voxelise
+    rows = []
+
+    def run(name, pl, Yd, c, iters, tol):
+        g = c.geom
+        p = cb.FbsParams(mu=c.mu, iters=iters, eps=c.eps, trace_energy=True, tol=tol)
+        cb.fbs_solve(pl, Yd, cb.FbsParams(mu=c.mu, iters=iters, eps=c.eps))  # beta setup
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f, rep = cb.fbs_solve(pl, Yd, p)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        truth = voxelise(g, c.phantom, sub=2)
+        mask = fov_mask(g)
+        fn = f.cpu().double().numpy()
+        err = np.linalg.norm((fn - truth)[mask]) / np.linalg.norm(truth[mask])
+        rows.append({"case": name, "iters": list(iters), "tol": tol,
+                     "level_iters": list(rep.level_iters), "E": rep.E, "E_eps": rep.E_eps,
+                     "rel_l2_fov": err, "change": list(rep.change)[:len(iters)], "solve_s": dt})
+        log("converge %s %s tol %g: made %s, E %.6e, fov %.4f, %.1f s"
+            % (name, iters, tol, rep.level_iters, rep.E, err, dt))
+
+    tc = tiny_case()
+    tp = cb.Plan(tc.geom)
+    tY = torch.as_tensor(tc.Y, dtype=torch.float32, device="cuda")
+    run("tiny", tp, tY, tc, (10,), 0.0)
+    run("tiny", tp, tY, tc, (5000,), 1e-6)
+    run("head", plan, Y, case, (20, 20), 0.0)
+    run("head", plan, Y, case, (300, 300, 1500), 1e-5)
+    return rows
+
+
 def tiny_recon_times(torch, cb):
     """Seconds per reconstruction of the 64^3 / 16-view workload (10
     iterations): the FP64 oracle on the host cores and the GPU solve, each
@@ -571,6 +612,10 @@ def main():
         "paper_context": "77-130 s per reconstruction on a Tesla C1060 (different "
                          "hardware, phantom and iteration count; not a target)",
     }
+    if args.converge:
+        t = time.perf_counter()
+        out["convergence"] = convergence_study(torch, cb, plan, case, Y)
+        log("convergence study %.1f s" % (time.perf_counter() - t))
     if not args.no_lowdose:
         t = time.perf_counter()
         out["lowdose"] = lowdose_sweep(torch, cb)
