@@ -252,12 +252,12 @@ __global__ __launch_bounds__(256) void k_project_tile(
             const int g0 = b0[2] * pxy + b0[1] * px + b0[0];
             for (int t = tid; t < RXP * RY * RZ; t += 256) {
                 const int row = (int)(((float)t + 0.5f) * ipx);
-                const int x = t - row * RXP;
+                const int x = t - __mul24(row, RXP);
                 const int rz = (int)(((float)row + 0.5f) * ipy);
-                const int ry = row - rz * RY;
+                const int ry = row - __mul24(rz, RY);
                 if (x < RX)
                     vol[t] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                                           gvol, (g0 + rz * pxy + ry * px + x) * 4,
+                                                           gvol, (g0 + __mul24(rz, pxy) + __mul24(ry, px) + x) * 4,
                                                            0, 0));
             }
         }
