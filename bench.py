@@ -630,6 +630,24 @@ def main():
         out["tiny_recon_64cubed_16views"] = tiny_recon_times(torch, cb)
         log("cpu baseline %.1f s" % (time.perf_counter() - t))
     print(json.dumps(out), flush=True)
+    leftover_processes()
+
+
+def leftover_processes():
+    """Log (stderr) any child process still alive when the benchmark ends."""
+    try:
+        import psutil
+        kids = psutil.Process().children(recursive=True)
+    except Exception as e:  # diagnostics only
+        log("child-process check unavailable: %r" % (e,))
+        return
+    if not kids:
+        log("no child processes left")
+    for k in kids:
+        try:
+            log("child process left: pid %d %s" % (k.pid, " ".join(k.cmdline())[:200]))
+        except Exception:
+            log("child process left: pid %d" % k.pid)
 
 
 if __name__ == "__main__":
