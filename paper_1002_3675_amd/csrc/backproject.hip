@@ -8,16 +8,16 @@
 //   * a cell c = (cx, cy, cz), c_a in [-1, N_a - 1], is the box between
 //     voxel centres c and c + 1; every projector sample lies in exactly one
 //     cell, the one given by the projector's own cell arithmetic;
-//   * preparation (geometry only, once per workspace): the ray increment
-//     of every pixel of every view, and every brick's pixel rectangle per
-//     view (its footprint on the detector);
-//   * pass 1 (one lane per cell, a workgroup per 8x16x2 brick of cells): for
-//     every view the workgroup copies the ray increments (double) and
-//     residuals of its brick's footprint into LDS; each lane then visits
-//     the pixels whose rays can cross its cell, enumerates the samples of
-//     each such ray that fall in the cell, and accumulates
-//     r * (trilinear corner weight) into eight register accumulators, one
-//     per cell corner;
+//   * preparation (geometry only, once per plan or workspace): the ray
+//     increment of every pixel of every view, and every brick's pixel
+//     rectangle per view (its footprint on the detector);
+//   * pass 1 (one lane per cell, a workgroup per 16x16x1 brick of cells):
+//     for every view the workgroup stages, per pixel of its brick's
+//     footprint, the candidate-range terms, the segment origin of the ray
+//     in the brick and the residual in LDS; each lane then visits the
+//     pixels whose rays can cross its cell, enumerates the samples of each
+//     such ray that fall in the cell, and accumulates r * (trilinear
+//     corner weight), in x-moment form, into eight register accumulators;
 //   * pass 2 (one lane per voxel): sum the matching corner of the eight
 //     cells that share the voxel, optionally fused with Step 1 of
 //     Algorithm A1, g = f - tau * P^T r.
