@@ -39,6 +39,14 @@ constexpr int CB_X = 16, CB_Y = 16, CB_Z = 1;  // cells per workgroup: one z lay
 constexpr int TABLE = CBCT_CELL_TABLE;         // pixels staged per view (60 B each)
 constexpr int G_BX = 64, G_BY = 4;            // pass-2 block
 
+// Row pitch (in elements) of the cell corner-sum array: nx + 1 cells
+// rounded up to 32, so that every brick row of cells (16 consecutive x
+// cells, starting at a multiple of 16) is a whole, aligned 64-byte segment
+// for float and the rows of a plane start on 128-byte boundaries.
+__host__ __device__ __forceinline__ long long cell_pitch(int nx) {
+    return ((long long)nx + 1 + 31) & ~31LL;
+}
+
 // Ray table entry per pixel and view (prepared once): the ray increment D
 // in double (segment origins).  Readers form the reciprocals of its float
 // rounding for the range estimates themselves (ray_inv).  24 bytes.
@@ -439,23 +447,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
     const int cy = bb.c0[1] + (tid / CB_X) % CB_Y;
     const int cz = bb.c0[2] + tid / (CB_X * CB_Y);
     const bool valid = cx < gc.nx && cy < gc.ny && cz < gc.nz;
-    // the brick in index coordinates: cells c0 .. c1 cover [c0, c1 + 1)
-    const float blo[3] = {(float)bb.c0[0], (float)bb.c0[1], (float)bb.c0[2]};
-    const float bhi[3] = {(float)min(bb.c0[0] + CB_X, gc.nx), (float)min(bb.c0[1] + CB_Y, gc.ny),
-                          (float)min(bb.c0[2] + CB_Z, gc.nz)};
-    // this lane's cell faces in z (same expressions as the brick box)
-    const float za = gc.z0 + (float)cz * gc.hz, zb = gc.z0 + (float)(cz + 1) * gc.hz;
-    const float cxf = (float)cx, cyf = (float)cy, czf = (float)cz;
-    // largest |c_a| over the brick's cells, for the staged range margins
-    const float cmax[3] = {fmaxf(fabsf(blo[0]), fabsf(bhi[0])), fmaxf(fabsf(blo[1]), fabsf(bhi[1])),
-                           fmaxf(fabsf(blo[2]), fabsf(bhi[2]))};
-    // the brick's single z layer (CB_Z = 1): cell cz0 = blo[2]
+    // the brick's single z layer (CB_Z = 1): cell cz0 = blo[2] below
     static_assert(CB_Z == 1, "the staged z bounds assume one z layer per brick");
     T acc[8];
 #pragma unroll
     for (int o = 0; o < 8; ++o) acc[o] = T(0);
 
     for (int k = 0; k < nviews; ++k) {
+        // Per-view copies of brick and lane constants.  They are formed
+        // again in every view from copies passed through an empty asm
+        // statement: held across the view loop instead, they would be
+        // spilled under the register budget.
+        int c0[3] = {bb.c0[0], bb.c0[1], bb.c0[2]}, lx = cx, ly = cy;
+        asm volatile("" : "+s"(c0[0]), "+s"(c0[1]), "+s"(c0[2]), "+v"(lx), "+v"(ly));
+        // the brick in index coordinates: cells c0 .. c1 cover [c0, c1 + 1)
+        const float blo[3] = {(float)c0[0], (float)c0[1], (float)c0[2]};
+        const float bhi[3] = {(float)min(c0[0] + CB_X, gc.nx), (float)min(c0[1] + CB_Y, gc.ny),
+                              (float)min(c0[2] + CB_Z, gc.nz)};
+        // this lane's cell faces in z (same expressions as the brick box)
+        const float za = gc.z0 + (float)cz * gc.hz, zb = gc.z0 + (float)(cz + 1) * gc.hz;
+        const float cxf = (float)lx, cyf = (float)ly, czf = (float)cz;
+        // largest |c_a| over the brick's cells, for the staged range margins
+        const float cmax[3] = {fmaxf(fabsf(blo[0]), fabsf(bhi[0])),
+                               fmaxf(fabsf(blo[1]), fabsf(bhi[1])),
+                               fmaxf(fabsf(blo[2]), fabsf(bhi[2]))};
         const ViewConst vc = views[k];
         const long long vbase = (long long)k * nu * nv;
         const T *rk = r + vbase;
@@ -485,7 +500,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
             // element t -> (row, col) by a float reciprocal: exact for
             // t < 2^13, since (t + 1/2)/bw stays >= 1/(2 bw) from an integer
             const float ibw = 1.0f / (float)bw;
-            for (int t = tid; t < bw * bh; t += 256) {
+            int t0 = tid;
+            asm volatile("" : "+v"(t0));
+            for (int t = t0; t < bw * bh; t += 256) {
                 const int row = (int)(((float)t + 0.5f) * ibw);
                 const int col = t - row * bw;
                 const long long pix = (long long)(bj0 + row) * nu + (bi0 + col);
@@ -604,8 +621,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
         }
     }
     if (!valid) return;
-    const long long ncell = (long long)(gc.nx + 1) * (gc.ny + 1) * (gc.nz + 1);
-    const long long lin = (long long)(cx + 1) + (long long)(gc.nx + 1) * ((cy + 1) + (long long)(gc.ny + 1) * (cz + 1));
+    // The cell's index is formed again from the launch coordinates (passed
+    // through an empty asm statement so the compiler does not keep the
+    // first computation alive across the view loop, where it would spill).
+    int b = (int)blockIdx.x, t = tid;
+    asm volatile("" : "+v"(t), "+s"(b));
+    const int br = xcd_tile(b, nb);
+    const int ox = (br % nbx) * CB_X + t % CB_X;                       // cx + 1
+    const int oy = ((br / nbx) % nby) * CB_Y + (t / CB_X) % CB_Y;      // cy + 1
+    const int oz = (br / (nbx * nby)) * CB_Z + t / (CB_X * CB_Y);      // cz + 1
+    const long long cp = cell_pitch(gc.nx);
+    const long long ncell = cp * (gc.ny + 1) * (gc.nz + 1);
+    const long long lin = (long long)ox + cp * (oy + (long long)(gc.ny + 1) * oz);
     T out[8];
     if constexpr (sizeof(T) == 4) {
         moments_to_corners(acc, out);
@@ -627,7 +654,7 @@ __global__ __launch_bounds__(256) void k_gather(GridConst gc, const T *__restric
     const int iy = blockIdx.y * G_BY + threadIdx.y;
     const int iz = blockIdx.z;
     if (ix >= gc.nx || iy >= gc.ny) return;
-    const long long cxn = gc.nx + 1, cxyn = cxn * (gc.ny + 1);
+    const long long cxn = cell_pitch(gc.nx), cxyn = cxn * (gc.ny + 1);
     const long long ncell = cxyn * (gc.nz + 1);
     // cell (ix - ox, iy - oy, iz - oz) is stored at (ix - ox + 1, ...)
     const long long base = (long long)(ix + 1) + cxn * (iy + 1) + cxyn * (iz + 1);
@@ -732,7 +759,7 @@ GeomLayout geom_layout(const cbct_geom &g) {
 }  // namespace
 
 size_t bp_cells_bytes(const cbct_geom &g, size_t elem) {
-    return align256(elem * 8 * (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1));
+    return align256(elem * 8 * (size_t)cell_pitch(g.nx) * (g.ny + 1) * (g.nz + 1));
 }
 
 size_t bp_geom_bytes(const cbct_geom &g) { return geom_layout(g).total; }

@@ -49,6 +49,8 @@ def test_head_full_schedule_matches_oracle():
     got = vol.ravel()[mk.sample_indices(case)]
     ref = np.array(want["samples"])
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print("head solve: E rel %.2e, samples rel L2 %.2e"
+          % (abs(rep.E - want["E"]) / want["E"], err), flush=True)
     assert err <= 1e-3, err
     # every z plane: L2 norm and sum
     tot = np.linalg.norm(vol)
@@ -67,6 +69,7 @@ def test_head_full_schedule_matches_oracle():
         rn = np.linalg.norm(ref)
         if rn > 0.0:
             err = np.linalg.norm(vol[k] - ref) / rn
+            print("head solve: plane %d rel L2 %.2e" % (k, err), flush=True)
             assert err <= 1e-3, (k, err)
         else:
             assert np.linalg.norm(vol[k]) <= 1e-3 * rms_plane, (k, np.linalg.norm(vol[k]))
