@@ -148,6 +148,153 @@ __global__ __launch_bounds__(256) void k_tv_sweep(TvArgs a, const float *__restr
     }
 }
 
+// The same step with 16-byte accesses: one wavefront per 32 x 8 tile, each
+// lane owning four consecutive x voxels of one row (nx a multiple of 4,
+// arrays 16-byte aligned).  z planes are staged in LDS with float4 loads
+// (plus the two x-halo columns), g is read and the result written as
+// float4, and the barriers are those of a single wavefront.  The
+// arithmetic per voxel is that of k_tv_sweep, in the same order.
+constexpr int W_X = 32, W_Y = 8;  // tile
+constexpr int W_PITCH = 40;       // LDS row: column 3 is x = i0 - 1, 4..35 the tile, 36 x = i0 + 32
+
+__global__ __launch_bounds__(64) void k_tv_sweep4(TvArgs a, const float *__restrict__ z,
+                                                  const float *__restrict__ g,
+                                                  float *__restrict__ out, float beta, float step,
+                                                  int nonneg) {
+    // z planes k and k+1: rows y = j0 - 1 .. j0 + 8
+    __shared__ __attribute__((aligned(16))) float zs[2][W_Y + 2][W_PITCH];
+    // p_x and p_y of plane k: rows y = j0 - 1 .. j0 + 7, columns as zs
+    __shared__ __attribute__((aligned(16))) float ps[2][W_Y + 1][W_PITCH];
+    const int lane = threadIdx.x;
+    const int tx = lane & 7, ty = lane >> 3;
+    const SweepTile st = sweep_tile(a, blockIdx.x);
+    const int i0 = st.i0, j0 = st.j0, k0 = st.k0, k1 = st.k1;
+    const int i = i0 + 4 * tx, j = j0 + ty;  // this lane's first voxel
+    const bool own = i < a.nx && j < a.ny;   // all four, since 4 | nx
+    const long long sy = a.nx, sz = (long long)a.nx * a.ny;
+
+    // staging work of this lane: interior float4 (row r1 = ty, and for
+    // lanes 0..15 also row 8 + lane / 8), or for lanes 16..35 one x-halo
+    // element (row (lane - 16) / 2, column low or high)
+    const int rB = lane < 16 ? 8 + (lane >> 3) : -1;           // second interior row
+    const int hrow = (lane >= 16 && lane < 36) ? (lane - 16) >> 1 : -1;
+    const int hcol = (lane & 1) ? 36 : 3;                        // LDS column of the halo
+    const int hx = (lane & 1) ? i0 + W_X : i0 - 1;               // its x
+    auto row_ok = [&](int r) {
+        const int y = j0 - 1 + r;
+        return r >= 0 && y >= 0 && y < a.ny;
+    };
+    const bool qA = i < a.nx && row_ok(ty);
+    const bool qB = rB >= 0 && i < a.nx && row_ok(rB);
+    const bool qH = hrow >= 0 && hx >= 0 && hx < a.nx && row_ok(hrow);
+    const long long oA = (long long)i + sy * (j0 - 1 + ty);
+    const long long oB = (long long)i + sy * (j0 - 1 + rB);
+    const long long oH = (long long)hx + sy * (j0 - 1 + hrow);
+    struct Plane {
+        float4 A, B;
+        float H;
+    };
+    auto fetch = [&](int k, Plane &pl) {
+        const bool kin = k < a.nz;
+        pl.A = (kin && qA) ? *(const float4 *)(z + oA + sz * k) : make_float4(0.f, 0.f, 0.f, 0.f);
+        pl.B = (kin && qB) ? *(const float4 *)(z + oB + sz * k) : make_float4(0.f, 0.f, 0.f, 0.f);
+        pl.H = (kin && qH) ? z[oH + sz * k] : 0.0f;
+    };
+    auto put = [&](int slot, const Plane &pl) {
+        *(float4 *)&zs[slot][ty][4 + 4 * tx] = pl.A;
+        if (rB >= 0) *(float4 *)&zs[slot][rB][4 + 4 * tx] = pl.B;
+        if (hrow >= 0) zs[slot][hrow][hcol] = pl.H;
+    };
+
+    // p_z of the plane below the chunk, for this lane's voxels
+    float pz_prev[4] = {0.f, 0.f, 0.f, 0.f};
+    if (own && k0 > 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const long long v = i + q + sy * j + sz * (k0 - 1);
+            const float zc = z[v];
+            const float gx = (i + q < a.nx - 1) ? (z[v + 1] - zc) * a.ihx : 0.0f;
+            const float gy = (j < a.ny - 1) ? (z[v + sy] - zc) * a.ihy : 0.0f;
+            const float gz = (z[v + sz] - zc) * a.ihz;  // k0 - 1 < nz - 1
+            pz_prev[q] = gz * __builtin_amdgcn_rsqf(gx * gx + gy * gy + gz * gz + a.eps2);
+        }
+    }
+    Plane nxt;
+    fetch(k0, nxt);
+    put(k0 & 1, nxt);
+    fetch(k0 + 1, nxt);
+    // the lane's extra p position: low x column (x = i0 - 1, 9 rows) for
+    // lanes 0..8, low y row (y = j0 - 1, 32 columns) for lanes 9..40
+    const int ex_r = lane < 9 ? lane : (lane < 41 ? 0 : -1);
+    const int ex_c = lane < 9 ? 3 : 4 + (lane - 9);
+    const int ex_x = i0 - 1 + (ex_c - 3), ex_y = j0 - 1 + ex_r;
+    for (int k = k0; k < k1; ++k) {
+        const int A = k & 1, B = A ^ 1;
+        put(B, nxt);                             // plane k + 1
+        if (k + 2 < k1 + 1) fetch(k + 2, nxt);  // in flight during this plane
+        const long long v = i + sy * j + sz * k;
+        const float4 gv = own ? *(const float4 *)(g + v) : make_float4(0.f, 0.f, 0.f, 0.f);
+        __syncthreads();
+        // p at the lane's own four positions (row ty + 1 of ps)
+        const int r = ty + 1, c = 4 + 4 * tx;
+        const float4 zc4 = *(const float4 *)&zs[A][r][c];
+        const float zr = zs[A][r][c + 4];
+        const float4 zu4 = *(const float4 *)&zs[A][r + 1][c];
+        const float4 zn4 = *(const float4 *)&zs[B][r][c];
+        const float zcv[4] = {zc4.x, zc4.y, zc4.z, zc4.w};
+        const float zxn[4] = {zc4.y, zc4.z, zc4.w, zr};
+        const float zyn[4] = {zu4.x, zu4.y, zu4.z, zu4.w};
+        const float zzn[4] = {zn4.x, zn4.y, zn4.z, zn4.w};
+        float px[4], py[4], pz[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float gx = (i + q < a.nx - 1) ? (zxn[q] - zcv[q]) * a.ihx : 0.0f;
+            const float gy = (j < a.ny - 1) ? (zyn[q] - zcv[q]) * a.ihy : 0.0f;
+            const float gz = (k < a.nz - 1) ? (zzn[q] - zcv[q]) * a.ihz : 0.0f;
+            const float inv = __builtin_amdgcn_rsqf(gx * gx + gy * gy + gz * gz + a.eps2);
+            px[q] = gx * inv;
+            py[q] = gy * inv;
+            pz[q] = gz * inv;
+        }
+        *(float4 *)&ps[0][r][c] = make_float4(px[0], px[1], px[2], px[3]);
+        *(float4 *)&ps[1][r][c] = make_float4(py[0], py[1], py[2], py[3]);
+        if (ex_r >= 0) {
+            // p at the low halo position (only p_x or p_y is read there)
+            const float zc = zs[A][ex_r][ex_c];
+            const float gx = (ex_x < a.nx - 1) ? (zs[A][ex_r][ex_c + 1] - zc) * a.ihx : 0.0f;
+            const float gy = (ex_y < a.ny - 1) ? (zs[A][ex_r + 1][ex_c] - zc) * a.ihy : 0.0f;
+            const float gz = (k < a.nz - 1) ? (zs[B][ex_r][ex_c] - zc) * a.ihz : 0.0f;
+            const float inv = __builtin_amdgcn_rsqf(gx * gx + gy * gy + gz * gz + a.eps2);
+            ps[0][ex_r][ex_c] = gx * inv;
+            ps[1][ex_r][ex_c] = gy * inv;
+        }
+        __syncthreads();
+        if (own) {
+            const float4 pl = *(const float4 *)&ps[0][r][c - 4];  // columns c - 4 .. c - 1
+            const float4 pu = *(const float4 *)&ps[1][r - 1][c];
+            const float pxm[4] = {pl.w, px[0], px[1], px[2]};
+            const float pym[4] = {pu.x, pu.y, pu.z, pu.w};
+            const float gvv[4] = {gv.x, gv.y, gv.z, gv.w};
+            float res[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float div = 0.0f;
+                if (i + q < a.nx - 1) div -= px[q] * a.ihx;
+                if (j < a.ny - 1) div -= py[q] * a.ihy;
+                if (k < a.nz - 1) div -= pz[q] * a.ihz;
+                if (i + q > 0) div += pxm[q] * a.ihx;
+                if (j > 0) div += pym[q] * a.ihy;
+                if (k > 0) div += pz_prev[q] * a.ihz;
+                float zn = zcv[q] - step * (div + beta * (zcv[q] - gvv[q]));
+                if (nonneg) zn = fmaxf(zn, 0.0f);
+                res[q] = zn;
+                pz_prev[q] = pz[q];
+            }
+            *(float4 *)(out + v) = make_float4(res[0], res[1], res[2], res[3]);
+        }
+    }
+}
+
 // Per-block partial sums of |Dz| and sqrt(|Dz|^2 + eps^2), in double.
 __global__ __launch_bounds__(256) void k_tv_energy(TvArgs a, const float *__restrict__ z,
                                                    double eps2, double *__restrict__ partials) {
@@ -216,8 +363,14 @@ hipError_t launch_tv_sweep(const GridConst &gc, const float *z, const float *g, 
     const TvArgs a = args_of(gc, eps);
     const int grid = ((gc.nx + ST_X - 1) / ST_X) * ((gc.ny + ST_Y - 1) / ST_Y) *
                      ((gc.nz + a.zc - 1) / a.zc);
-    hipLaunchKernelGGL(k_tv_sweep, dim3(grid), dim3(256), 0, s, a, z, g, out, beta, step,
-                       nonneg);
+    const bool vec4 = gc.nx % 4 == 0 && ((uintptr_t)z | (uintptr_t)g | (uintptr_t)out) % 16 == 0;
+    static_assert(W_X == ST_X && W_Y == ST_Y, "both sweeps use the same tiles");
+    if (vec4)
+        hipLaunchKernelGGL(k_tv_sweep4, dim3(grid), dim3(64), 0, s, a, z, g, out, beta, step,
+                           nonneg);
+    else
+        hipLaunchKernelGGL(k_tv_sweep, dim3(grid), dim3(256), 0, s, a, z, g, out, beta, step,
+                           nonneg);
     return hipGetLastError();
 }
 
