@@ -175,12 +175,14 @@ __device__ __forceinline__ double march_double(const double Q[3], const double D
 // segment-origin work over twice the samples.
 constexpr int TILE_U = 16, TILE_V = 16, TILE_CH = 32;
 constexpr int TILE_LDS = 4096;  // floats
+constexpr int BOX_TAB = 64;     // chunk boxes computed together
 
 __global__ __launch_bounds__(256) void k_project_tile(
     const ViewConst *__restrict__ views, DetConst dc, GridConst gc, int nu, int nv,
     const float *__restrict__ fp, int fp_elems, const float *__restrict__ Y,
     float *__restrict__ out, double *__restrict__ partials, float step, int margin) {
     __shared__ float vol[TILE_LDS];
+    __shared__ int4 boxes[BOX_TAB];  // chunk boxes, packed (b0 | b1 << 16 per axis)
     __shared__ int red[2][4];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
@@ -209,114 +211,151 @@ __global__ __launch_bounds__(256) void k_project_tile(
     __syncthreads();
     lo = min(min(red[0][0], red[0][1]), min(red[0][2], red[0][3]));
     hi = max(max(red[1][0], red[1][1]), max(red[1][2], red[1][3]));
-    // corner rays of the tile (identical in every lane)
-    const int ci0 = tu * TILE_U, ci1 = min(ci0 + TILE_U - 1, nu - 1);
-    const int cj0 = tv * TILE_V, cj1 = min(cj0 + TILE_V - 1, nv - 1);
-    double Dc[4][3], Qc[3];
-    ray_setup(vc, dc, ci0, cj0, Qc, Dc[0]);
-    ray_setup(vc, dc, ci1, cj0, Qc, Dc[1]);
-    ray_setup(vc, dc, ci0, cj1, Qc, Dc[2]);
-    ray_setup(vc, dc, ci1, cj1, Qc, Dc[3]);
     const int N[3] = {gc.nx, gc.ny, gc.nz};
     const int px = gc.nx + 2, pxy = px * (gc.ny + 2);
     const __amdgpu_buffer_rsrc_t gvol =
         __builtin_amdgcn_make_buffer_rsrc((void *)fp, (short)0, fp_elems * 4, 0x00020000);
     double acc = 0.0;
-    for (int nc = lo & ~(TILE_CH - 1); nc <= hi; nc += TILE_CH) {
-        // box of padded cells [b0, b1] per axis touched by this chunk
-        int b0[3], b1[3];
+    // chunk c holds the sample indices nc0 + TILE_CH c .. nc0 + TILE_CH c + TILE_CH - 1
+    const int nc0 = lo & ~(TILE_CH - 1);
+    const int nchunks = hi >= nc0 ? (hi - nc0) / TILE_CH + 1 : 0;
+    for (int cg = 0; cg < nchunks; cg += BOX_TAB) {
+        __syncthreads();  // readers of the previous group's boxes are done
+        if (tid < BOX_TAB && cg + tid < nchunks) {
+            // box of padded cells [b0, b1] per axis touched by chunk cg + tid,
+            // from the tile's four corner rays
+            const int nc = nc0 + TILE_CH * (cg + tid);
+            const int ci0 = tu * TILE_U, ci1 = min(ci0 + TILE_U - 1, nu - 1);
+            const int cj0 = tv * TILE_V, cj1 = min(cj0 + TILE_V - 1, nv - 1);
+            double Dc[4][3], Qc[3];
+            ray_setup(vc, dc, ci0, cj0, Qc, Dc[0]);
+            ray_setup(vc, dc, ci1, cj0, Qc, Dc[1]);
+            ray_setup(vc, dc, ci0, cj1, Qc, Dc[2]);
+            ray_setup(vc, dc, ci1, cj1, Qc, Dc[3]);
+            int pk[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            double qmin = 1e300, qmax = -1e300;
+            for (int a = 0; a < 3; ++a) {
+                double qmin = 1e300, qmax = -1e300;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const double qa = Qc[a] + (double)nc * Dc[c][a];
-                const double qb = Qc[a] + (double)(nc + TILE_CH - 1) * Dc[c][a];
-                qmin = fmin(qmin, fmin(qa, qb));
-                qmax = fmax(qmax, fmax(qa, qb));
+                for (int c = 0; c < 4; ++c) {
+                    const double qa = Qc[a] + (double)nc * Dc[c][a];
+                    const double qb = Qc[a] + (double)(nc + TILE_CH - 1) * Dc[c][a];
+                    qmin = fmin(qmin, fmin(qa, qb));
+                    qmax = fmax(qmax, fmax(qa, qb));
+                }
+                // cells floor(q) in [-1, N-1] read padded indices cell+1 and
+                // cell+2; an empty range keeps b0 > b1 after the clamps
+                const int b0 = min(max((int)floor(fmax(qmin, -4.0)) - margin + 1, 0), N[a] + 2);
+                const int b1 =
+                    max(min((int)floor(fmin(qmax, (double)N[a] + 4.0)) + margin + 2, N[a] + 1), -1);
+                pk[a] = (b0 & 0xffff) | (b1 << 16);
             }
-            // cells floor(q) in [-1, N-1] read padded indices cell+1 and cell+2
-            b0[a] = max((int)floor(fmax(qmin, -4.0)) - margin + 1, 0);
-            b1[a] = min((int)floor(fmin(qmax, (double)N[a] + 4.0)) + margin + 2, N[a] + 1);
-        }
-        const int RX = b1[0] - b0[0] + 1, RY = b1[1] - b0[1] + 1, RZ = b1[2] - b0[2] + 1;
-        // LDS rows have an odd pitch, so rays spread across rows (views whose
-        // rays run along x) do not pile onto one bank
-        const int RXP = RX | 1;
-        const bool staged = RX > 0 && RY > 0 && RZ > 0 && RXP * RY * RZ <= TILE_LDS;
-        __syncthreads();  // the previous chunk's readers are done
-        if (staged) {
-            // element t -> (x, row) -> (y, z), by float reciprocals: exact for
-            // t < 2^13 since (t + 1/2)/pitch stays >= 1/(2 pitch) from an integer
-            const float ipx = 1.0f / (float)RXP, ipy = 1.0f / (float)RY;
-            const int g0 = b0[2] * pxy + b0[1] * px + b0[0];
-            for (int t = tid; t < RXP * RY * RZ; t += 256) {
-                const int row = (int)(((float)t + 0.5f) * ipx);
-                const int x = t - __mul24(row, RXP);
-                const int rz = (int)(((float)row + 0.5f) * ipy);
-                const int ry = row - __mul24(rz, RY);
-                if (x < RX)
-                    vol[t] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                                           gvol, (g0 + __mul24(rz, pxy) + __mul24(ry, px) + x) * 4,
-                                                           0, 0));
-            }
+            boxes[tid] = make_int4(pk[0], pk[1], pk[2], 0);
         }
         __syncthreads();
-        const int na = max(n0, nc), nb = min(n1, nc + TILE_CH - 1);
-        if (na > nb) continue;
-        const int s = nc & ~(SEG - 1);
-        const SegOrigin o = seg_origin(Q, D, s);
-        float seg = 0.0f;
-        if (staged) {
-            const int RX = RXP;  // row pitch in LDS
-            const int RXY = RX * RY;
-            const float RXf = (float)RX, RXYf = (float)RXY;
-            const int base = (o.I[2] + 1 - b0[2]) * RXY + (o.I[1] + 1 - b0[1]) * RX +
-                             (o.I[0] + 1 - b0[0]);
-            float m = (float)(na - s);
-            for (int n = na; n <= nb; ++n, m += 1.0f) {
-                // seg_axis's coordinates and weights; the LDS offset of the
-                // floors is formed in float (exact: |offset| < 2^24)
-                const float lx = __builtin_fmaf(m, Df[0], o.f[0]);
-                const float ly = __builtin_fmaf(m, Df[1], o.f[1]);
-                const float lz = __builtin_fmaf(m, Df[2], o.f[2]);
-                const float fx = __builtin_floorf(lx), fy = __builtin_floorf(ly),
-                            fz = __builtin_floorf(lz);
-                const float wx = lx - fx, wy = ly - fy, wz = lz - fz;
-                const float *p =
-                    vol + base + (int)__builtin_fmaf(fz, RXYf, __builtin_fmaf(fy, RXf, fx));
-                const float c00 = p[0] + wx * (p[1] - p[0]);
-                const float c10 = p[RX] + wx * (p[RX + 1] - p[RX]);
-                const float c01 = p[RXY] + wx * (p[RXY + 1] - p[RXY]);
-                const float c11 = p[RXY + RX] + wx * (p[RXY + RX + 1] - p[RXY + RX]);
-                const float c0 = c00 + wy * (c10 - c00);
-                const float c1 = c01 + wy * (c11 - c01);
-                seg += c0 + wz * (c1 - c0);
+        const int cend = min(nchunks, cg + BOX_TAB);
+        for (int c = cg; c < cend; ++c) {
+            const int nc = nc0 + TILE_CH * c;
+            const int4 bp = boxes[c - cg];
+            // identical in every lane: kept in scalar registers
+            const int pk[3] = {__builtin_amdgcn_readfirstlane(bp.x),
+                               __builtin_amdgcn_readfirstlane(bp.y),
+                               __builtin_amdgcn_readfirstlane(bp.z)};
+            int b0[3], b1[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                b0[a] = (int)(short)(pk[a] & 0xffff);
+                b1[a] = pk[a] >> 16;
             }
-        } else {
-            const int base = (o.I[2] + 1) * pxy + (o.I[1] + 1) * px + (o.I[0] + 1);
-            float m = (float)(na - s);
-            for (int n = na; n <= nb; ++n, m += 1.0f) {
-                int dx, dy, dz;
-                float wx, wy, wz;
-                seg_axis(m, Df[0], o.f[0], dx, wx);
-                seg_axis(m, Df[1], o.f[1], dy, wy);
-                seg_axis(m, Df[2], o.f[2], dz, wz);
-                const int off = 4 * (base + dx + __mul24(dy, px) + __mul24(dz, pxy));
-                const float2 a0 = load_pair(gvol, off, 0);
-                const float2 a1 = load_pair(gvol, off, 4 * px);
-                const float2 c0v = load_pair(gvol, off, 4 * pxy);
-                const float2 c1v = load_pair(gvol, off, 4 * (pxy + px));
-                const float c00 = a0.x + wx * (a0.y - a0.x);
-                const float c10 = a1.x + wx * (a1.y - a1.x);
-                const float c01 = c0v.x + wx * (c0v.y - c0v.x);
-                const float c11 = c1v.x + wx * (c1v.y - c1v.x);
-                const float c0 = c00 + wy * (c10 - c00);
-                const float c1 = c01 + wy * (c11 - c01);
-                seg += c0 + wz * (c1 - c0);
+            const int RX = b1[0] - b0[0] + 1, RY = b1[1] - b0[1] + 1, RZ = b1[2] - b0[2] + 1;
+            // LDS rows have an odd pitch, so rays spread across rows (views whose
+            // rays run along x) do not pile onto one bank
+            const int RXP = RX | 1;
+            const bool staged = RX > 0 && RY > 0 && RZ > 0 && RXP * RY * RZ <= TILE_LDS;
+            __syncthreads();  // the previous chunk's readers are done
+            if (staged) {
+                // Plane z of the box is RXP * RY consecutive LDS elements, x
+                // fastest; each wavefront loads 64 consecutive elements
+                // straight into LDS.  Element t of a plane is row t / RXP, by
+                // a float reciprocal: exact for t < 2^13, since (t + 1/2)/RXP
+                // stays >= 1/(2 RXP) from an integer and the reciprocal and
+                // product err by under 2^-21 relative.
+                const int npl = RXP * RY;
+                const float ipx = __builtin_amdgcn_rcpf((float)RXP);
+                for (int rz = 0; rz < RZ; ++rz) {
+                    const int gpl = (b0[2] + rz) * pxy + b0[1] * px + b0[0];
+                    for (int t0 = 64 * wid; t0 < npl; t0 += 256) {
+                        const int t = t0 + lane;
+                        if (t < npl) {
+                            const int row = (int)(((float)t + 0.5f) * ipx);
+                            const int x = t - __mul24(row, RXP);
+                            // x = RX (the odd pitch's pad column, never read)
+                            // loads a neighbour or, past the end, zero
+                            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                                gvol, (__attribute__((address_space(3))) void *)&vol[rz * npl + t0],
+                                4, (gpl + __mul24(row, px) + x) * 4, 0, 0, 0);
+                        }
+                    }
+                }
+                __builtin_amdgcn_s_waitcnt(0);  // the loads have landed in LDS
             }
+            __syncthreads();
+            const int na = max(n0, nc), nb = min(n1, nc + TILE_CH - 1);
+            if (na > nb) continue;
+            const int s = nc & ~(SEG - 1);
+            const SegOrigin o = seg_origin(Q, D, s);
+            float seg = 0.0f;
+            if (staged) {
+                const int RX = RXP;  // row pitch in LDS
+                const int RXY = RX * RY;
+                const float RXf = (float)RX, RXYf = (float)RXY;
+                const int base = (o.I[2] + 1 - b0[2]) * RXY + (o.I[1] + 1 - b0[1]) * RX +
+                                 (o.I[0] + 1 - b0[0]);
+                float m = (float)(na - s);
+                for (int n = na; n <= nb; ++n, m += 1.0f) {
+                    // seg_axis's coordinates and weights; the LDS offset of the
+                    // floors is formed in float (exact: |offset| < 2^24)
+                    const float lx = __builtin_fmaf(m, Df[0], o.f[0]);
+                    const float ly = __builtin_fmaf(m, Df[1], o.f[1]);
+                    const float lz = __builtin_fmaf(m, Df[2], o.f[2]);
+                    const float fx = __builtin_floorf(lx), fy = __builtin_floorf(ly),
+                                fz = __builtin_floorf(lz);
+                    const float wx = lx - fx, wy = ly - fy, wz = lz - fz;
+                    const float *p =
+                        vol + base + (int)__builtin_fmaf(fz, RXYf, __builtin_fmaf(fy, RXf, fx));
+                    const float c00 = p[0] + wx * (p[1] - p[0]);
+                    const float c10 = p[RX] + wx * (p[RX + 1] - p[RX]);
+                    const float c01 = p[RXY] + wx * (p[RXY + 1] - p[RXY]);
+                    const float c11 = p[RXY + RX] + wx * (p[RXY + RX + 1] - p[RXY + RX]);
+                    const float c0 = c00 + wy * (c10 - c00);
+                    const float c1 = c01 + wy * (c11 - c01);
+                    seg += c0 + wz * (c1 - c0);
+                }
+            } else {
+                const int base = (o.I[2] + 1) * pxy + (o.I[1] + 1) * px + (o.I[0] + 1);
+                float m = (float)(na - s);
+                for (int n = na; n <= nb; ++n, m += 1.0f) {
+                    int dx, dy, dz;
+                    float wx, wy, wz;
+                    seg_axis(m, Df[0], o.f[0], dx, wx);
+                    seg_axis(m, Df[1], o.f[1], dy, wy);
+                    seg_axis(m, Df[2], o.f[2], dz, wz);
+                    const int off = 4 * (base + dx + __mul24(dy, px) + dz * pxy);
+                    const float2 a0 = load_pair(gvol, off, 0);
+                    const float2 a1 = load_pair(gvol, off, 4 * px);
+                    const float2 c0v = load_pair(gvol, off, 4 * pxy);
+                    const float2 c1v = load_pair(gvol, off, 4 * (pxy + px));
+                    const float c00 = a0.x + wx * (a0.y - a0.x);
+                    const float c10 = a1.x + wx * (a1.y - a1.x);
+                    const float c01 = c0v.x + wx * (c0v.y - c0v.x);
+                    const float c11 = c1v.x + wx * (c1v.y - c1v.x);
+                    const float c0 = c00 + wy * (c10 - c00);
+                    const float c1 = c01 + wy * (c11 - c01);
+                    seg += c0 + wz * (c1 - c0);
+                }
+            }
+            acc += (double)seg;
         }
-        acc += (double)seg;
     }
     double sq = 0.0;
     if (valid) {
