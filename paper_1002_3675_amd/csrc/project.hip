@@ -311,8 +311,9 @@ __global__ __launch_bounds__(256) void k_project_tile(
                 const float RXf = (float)RX, RXYf = (float)RXY;
                 const int base = (o.I[2] + 1 - b0[2]) * RXY + (o.I[1] + 1 - b0[1]) * RX +
                                  (o.I[0] + 1 - b0[0]);
-                float m = (float)(na - s);
-                for (int n = na; n <= nb; ++n, m += 1.0f) {
+                // m counts the samples in float (exact below 2^24)
+                const float mb = (float)(nb - s);
+                for (float m = (float)(na - s); m <= mb; m += 1.0f) {
                     // seg_axis's coordinates and weights; the LDS offset of the
                     // floors is formed in float (exact: |offset| < 2^24)
                     const float lx = __builtin_fmaf(m, Df[0], o.f[0]);
@@ -333,8 +334,8 @@ __global__ __launch_bounds__(256) void k_project_tile(
                 }
             } else {
                 const int base = (o.I[2] + 1) * pxy + (o.I[1] + 1) * px + (o.I[0] + 1);
-                float m = (float)(na - s);
-                for (int n = na; n <= nb; ++n, m += 1.0f) {
+                const float mb = (float)(nb - s);
+                for (float m = (float)(na - s); m <= mb; m += 1.0f) {
                     int dx, dy, dz;
                     float wx, wy, wz;
                     seg_axis(m, Df[0], o.f[0], dx, wx);

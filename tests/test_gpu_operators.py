@@ -58,6 +58,46 @@ def test_backproject_matches_oracle(name, g):
     assert rel_l2(f, want) <= TOL, rel_l2(f, want)
 
 
+# Slices of more than 2^23 voxels (2900 x 2900, 2902^2 padded): offsets of
+# the padded volume's planes exceed 24-bit integer products.  "staged":
+# voxels large against a pixel's footprint, so the projector stages its
+# chunk boxes in LDS; "global": voxels small, so its chunks read the volume
+# from memory.
+WIDE = {
+    "staged": Geometry(2900, 2900, 2, 1.0, 1.0, 1.0, 40, 6, 0.4, 0.4, 2500.0, 3000.0, 2,
+                       angles=(0.3, 1.9)),
+    "global": Geometry(2900, 2900, 2, 0.1, 0.1, 0.1, 40, 6, 3.2, 0.1, 600.0, 1000.0, 2,
+                       angles=(0.3, 1.9)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(WIDE))
+def test_wide_slices_match_oracle(name):
+    require_gpu()
+    g = WIDE[name]
+    _log("wide-slice parity %s" % name)
+    assert (g.nx + 2) * (g.ny + 2) > 2 ** 23
+    if name == "global":
+        # lower bound of a chunk box (as in fallback_margins): beyond the LDS box
+        import paper_1002_3675_amd as cb
+        cfg = cb.kernel_config()
+        half = 0.5 * math.sqrt((g.nx * g.hx) ** 2 + (g.ny * g.hy) ** 2 + (g.nz * g.hz) ** 2)
+        span_u = cfg["tile_u"] * g.au * (g.sad - half) / g.sdd / g.hx
+        depth = cfg["tile_chunk"] * 0.5 * g.hx / math.sqrt(3.0) / g.hx
+        assert math.floor(span_u) * (g.nz + 2) * math.floor(depth) > cfg["tile_lds_floats"]
+    rng = np.random.default_rng(15)
+    f = rng.uniform(0.0, 0.02, g.vol_shape).astype(np.float32).astype(np.float64)
+    plan = _plan(g)
+    y = to_np(plan.project(to_dev(f)))
+    want = oracle.project(g, f)
+    assert np.count_nonzero(want) > want.size // 4
+    assert rel_l2(y, want) <= TOL, rel_l2(y, want)
+    r = rng.uniform(0.0, 4.0, g.proj_shape).astype(np.float32).astype(np.float64)
+    b = to_np(plan.backproject(to_dev(r)))
+    want_b = oracle.backproject(g, r)
+    assert rel_l2(b, want_b) <= TOL, rel_l2(b, want_b)
+
+
 def test_backproject_signed_residual():
     """Mixed-sign input (a residual) still meets the tolerance."""
     require_gpu()
