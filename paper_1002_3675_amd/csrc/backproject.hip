@@ -246,19 +246,28 @@ struct RayRef {
     }
 };
 
-// Samples n0..n1 of a ray that fall in cell (cx, cy, cz), float data: o is
-// the origin of segment ns = n0 & ~(SEG - 1); a later segment's origin is
-// computed from the ray's double increment in the ray table.  The
-// projector's own cell arithmetic decides membership; a candidate outside
-// the cell adds zero (no branch in the loop body).
+// Candidate samples of a ray in cell (cx, cy, cz), float data: sample
+// indices sf * SEG + m for m from m0 to mlast (integer-valued floats, sf the
+// segment number, m0 < SEG; mlast may run into later segments); o is the
+// origin of segment sf.  A later segment's origin is computed from the
+// ray's double increment in the ray table.  The projector's own cell
+// arithmetic decides membership; a candidate outside the cell adds zero (no
+// branch in the loop body).
 __device__ __forceinline__ void cell_samples_f(float acc[8], float rv, const double Qd[3],
-                                               const RayRef &ray, SegOrigin o, int ns,
-                                               const float Df[3], int n0, int n1, int cx,
+                                               const RayRef &ray, SegOrigin o, float sf,
+                                               const float Df[3], float m, float mlast, int cx,
                                                int cy, int cz) {
 #pragma clang fp contract(off)
     // The projector puts sample m of the segment in cell I + floor(l) with
     // l = fma(m, Df, f), weight l - floor(l): the sample is in cell c when
     // floor(l) == L = c - I on every axis, and its weight is then l - L.
+    // With L an integer, w = l - L rounds to itself except for l in
+    // [-2^-25, 0) with L = -1, where it rounds up to 1; rounding keeps w's
+    // sign and its order against 1.  So floor(l) == L exactly when w, read as
+    // an unsigned integer, is below that of 1.0f (a negative w has its sign
+    // bit set, l - L = 0 gives +0), except when some w is exactly 1: then
+    // floor decides, as in the projector, in a second pass over the
+    // segment's candidates.
     float L[3];
     auto bounds = [&]() {
         L[0] = (float)(cx - o.I[0]);
@@ -266,26 +275,47 @@ __device__ __forceinline__ void cell_samples_f(float acc[8], float rv, const dou
         L[2] = (float)(cz - o.I[2]);
     };
     bounds();
-    float m = (float)(n0 - ns);
+    constexpr unsigned ONE = 0x3f800000u;  // 1.0f
     for (;;) {
-        // samples up to the end of this segment; m counts in float (exact)
-        const int nend = min(n1, ns + SEG - 1);
-        const float mend = (float)(nend - ns);
+        // samples up to the end of this segment (float counts are exact)
+        const float mend = __builtin_amdgcn_fmed3f(mlast, 0.0f, (float)(SEG - 1));  // mlast >= 0
+        const float mstart = m;
+        bool edge = false;  // some sample had a weight of exactly 1
         for (; m <= mend; m += 1.0f) {
-            const float lx = __builtin_fmaf(m, Df[0], o.f[0]);
-            const float ly = __builtin_fmaf(m, Df[1], o.f[1]);
-            const float lz = __builtin_fmaf(m, Df[2], o.f[2]);
-            const bool in = (__builtin_floorf(lx) == L[0]) & (__builtin_floorf(ly) == L[1]) &
-                            (__builtin_floorf(lz) == L[2]);
-            add_moments(acc, in ? rv : 0.0f, lx - L[0], ly - L[1], lz - L[2]);
+            const float wx = __builtin_fmaf(m, Df[0], o.f[0]) - L[0];
+            const float wy = __builtin_fmaf(m, Df[1], o.f[1]) - L[1];
+            const float wz = __builtin_fmaf(m, Df[2], o.f[2]) - L[2];
+            const unsigned wmax = max(max(__builtin_bit_cast(unsigned, wx),
+                                          __builtin_bit_cast(unsigned, wy)),
+                                      __builtin_bit_cast(unsigned, wz));
+            add_moments(acc, wmax < ONE ? rv : 0.0f, wx, wy, wz);
+            edge |= wmax == ONE;
         }
-        if (nend >= n1) return;
+        if (edge) {
+            // rare: add the samples with a weight of 1 that floor puts in
+            // the cell (after the others: the order of the sum changes, not
+            // its terms)
+            for (float mm = mstart; mm <= mend; mm += 1.0f) {
+                const float lx = __builtin_fmaf(mm, Df[0], o.f[0]);
+                const float ly = __builtin_fmaf(mm, Df[1], o.f[1]);
+                const float lz = __builtin_fmaf(mm, Df[2], o.f[2]);
+                const float wx = lx - L[0], wy = ly - L[1], wz = lz - L[2];
+                const unsigned wmax = max(max(__builtin_bit_cast(unsigned, wx),
+                                              __builtin_bit_cast(unsigned, wy)),
+                                          __builtin_bit_cast(unsigned, wz));
+                const bool in = (__builtin_floorf(lx) == L[0]) &
+                                (__builtin_floorf(ly) == L[1]) & (__builtin_floorf(lz) == L[2]);
+                if (wmax == ONE && in) add_moments(acc, rv, wx, wy, wz);
+            }
+        }
+        if (mlast <= (float)(SEG - 1)) return;
         // rare: the cell's samples of this ray run into the next segment
-        ns += SEG;
+        sf += 1.0f;
         m = 0.0f;
+        mlast -= (float)SEG;
         const PixelRay *gray = ray.get();
         const double D[3] = {gray->D[0], gray->D[1], gray->D[2]};
-        o = seg_origin(Qd, D, ns);
+        o = seg_origin(Qd, D, (int)sf * SEG);
         bounds();
     }
 }
@@ -380,13 +410,15 @@ __device__ __forceinline__ void visit_staged(float acc[8], const float cq[2], co
     const float lo = fmaxf(fmaxf(lx, ly), er.zlo);
     const float hi = fminf(fminf(hx, hy), er.zhi);
     if (!(lo <= hi)) return;
-    const int n0 = clamp_to_int(-floor_t(-lo));
-    const int n1 = clamp_to_int(floor_t(hi));
-    if (n0 > n1) return;
-    const int ns = n0 & ~(SEG - 1);
+    // first and last candidate sample, clamped as clamp_to_int clamps, kept
+    // in float (integers below 2^24 are exact)
+    const float n0 = __builtin_amdgcn_fmed3f(-floor_t(-lo), -4.0f, (float)(1 << 24));
+    const float n1 = __builtin_amdgcn_fmed3f(floor_t(hi), -4.0f, (float)(1 << 24));
+    if (!(n0 <= n1)) return;
+    const float sf = floor_t(n0 * (1.0f / SEG));  // segment number
     const StagedWalk &e = *ew;
     SegOrigin o;
-    if ((n0 >> 8) == (int)e.sq) {
+    if ((int)sf == (int)e.sq) {
         o.I[0] = e.I[0];
         o.I[1] = e.I[1];
         o.I[2] = e.I[2];
@@ -396,10 +428,11 @@ __device__ __forceinline__ void visit_staged(float acc[8], const float cq[2], co
     } else {
         const PixelRay *gray = ray.get();
         const double D[3] = {gray->D[0], gray->D[1], gray->D[2]};
-        o = seg_origin(Qd, D, ns);
+        o = seg_origin(Qd, D, (int)sf * SEG);
     }
     const float Df[3] = {e.Df[0], e.Df[1], e.Df[2]};
-    cell_samples_f(acc, e.r, Qd, ray, o, ns, Df, n0, n1, cx, cy, cz);
+    cell_samples_f(acc, e.r, Qd, ray, o, sf, Df, __builtin_fmaf(sf, -(float)SEG, n0),
+                   __builtin_fmaf(sf, -(float)SEG, n1), cx, cy, cz);
 }
 
 template <typename T>
@@ -416,7 +449,8 @@ __device__ __forceinline__ void visit_global(T acc[8], const CellRange &cr, cons
         const int ns = n0 & ~(SEG - 1);
         float Df[3];
         to_float3(D, Df);
-        cell_samples_f(acc, rv, Qd, ray, seg_origin(Qd, D, ns), ns, Df, n0, n1, cx, cy, cz);
+        cell_samples_f(acc, rv, Qd, ray, seg_origin(Qd, D, ns), (float)(ns / SEG), Df,
+                       (float)(n0 - ns), (float)(n1 - ns), cx, cy, cz);
     } else {
         cell_samples_d(acc, rv, Qd, D, n0, n1, cx, cy, cz);
     }
