@@ -91,6 +91,13 @@ struct StagedWalk {
     short sq;
 };
 
+// Both parts of a pixel's entry, side by side: one pointer reaches both.
+struct StagedEntry {
+    StagedRange rg;
+    StagedWalk wk;
+};
+static_assert(sizeof(StagedEntry) == 60, "60-byte LDS entries");
+
 __device__ __forceinline__ float inv_or_huge(float d) {
     return d != 0.0f ? __builtin_amdgcn_rcpf(d) : 1e30f;
 }
@@ -400,9 +407,9 @@ __global__ __launch_bounds__(256) void k_brick_rects(const ViewConst *__restrict
 // Accumulate the samples of one ray (residual rv) that fall in the cell:
 // from the LDS entries (float data) or from the ray table (either type).
 __device__ __forceinline__ void visit_staged(float acc[8], const float cq[2], const float kw[2],
-                                             const StagedRange &er, const StagedWalk *ew,
-                                             const RayRef &ray, const double Qd[3], int cx,
-                                             int cy, int cz) {
+                                             const StagedEntry &en, const RayRef &ray,
+                                             const double Qd[3], int cx, int cy, int cz) {
+    const StagedRange &er = en.rg;
     const float lx = __builtin_fmaf(cq[0], er.inv[0], er.lo[0]);
     const float ly = __builtin_fmaf(cq[1], er.inv[1], er.lo[1]);
     const float hx = lx + __builtin_fmaf(fabsf(er.inv[0]), kw[0], 2e-3f);
@@ -416,7 +423,7 @@ __device__ __forceinline__ void visit_staged(float acc[8], const float cq[2], co
     const float n1 = __builtin_amdgcn_fmed3f(floor_t(hi), -4.0f, (float)(1 << 24));
     if (!(n0 <= n1)) return;
     const float sf = floor_t(n0 * (1.0f / SEG));  // segment number
-    const StagedWalk &e = *ew;
+    const StagedWalk &e = en.wk;
     SegOrigin o;
     if ((int)sf == (int)e.sq) {
         o.I[0] = e.I[0];
@@ -466,8 +473,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
                                                const int4 *__restrict__ rects,
                                                const T *__restrict__ r, T *__restrict__ cells,
                                                T step) {
-    __shared__ StagedRange trange[TABLE];
-    __shared__ StagedWalk twalk[TABLE];
+    __shared__ StagedEntry table[TABLE];
     __shared__ float2 corner[(CB_X + 1) * (CB_Y + 1)];
     const int tid = threadIdx.x;
     // bricks x-fastest, then y, then z; each XCD takes one contiguous range,
@@ -584,8 +590,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
                 // sample indices below 32767 * SEG)
                 ew.sq = (short)min(sb / SEG, 32767);
                 ew.r = (float)rk[pix];
-                trange[t] = er;
-                twalk[t] = ew;
+                table[t].rg = er;
+                table[t].wk = ew;
             }
         }
         __syncthreads();
@@ -623,22 +629,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
         int i = i0, j = j0;
         if constexpr (sizeof(T) == 4) {
             if (staged) {
-                // entries of pixel (i, j): pointers advanced along the
+                // the entry of pixel (i, j): a pointer advanced along the
                 // rectangle (no per-visit multiplications)
-                const int e0 = (j0 - bj0) * bw + (i0 - bi0);
-                const StagedRange *pr = trange + e0;
-                const StagedWalk *pw = twalk + e0;
+                const StagedEntry *pe = table + (j0 - bj0) * bw + (i0 - bi0);
                 const int skip = bw - w;  // from a row's end to the next row's start
-                for (int q = 0; q < npix; ++q) {
-                    const RayRef ray{raysk, nu, i, j};
-                    visit_staged(acc, cr.cq, kw, *pr, pw, ray, vc.Qd, cx, cy, cz);
-                    ++pr;
-                    ++pw;
-                    if (++i > i1) {
-                        i = i0;
-                        ++j;
-                        pr += skip;
-                        pw += skip;
+                if (npix > 0) {
+                    for (;;) {
+                        const RayRef ray{raysk, nu, i, j};
+                        visit_staged(acc, cr.cq, kw, *pe, ray, vc.Qd, cx, cy, cz);
+                        ++pe;
+                        if (++i > i1) {
+                            if (++j > j1) break;
+                            i = i0;
+                            pe += skip;
+                        }
                     }
                 }
                 continue;
