@@ -507,9 +507,18 @@ def main():
         % (first_s, rep.beta_used, rep.n_inner_used))
     for _ in range(max(0, args.warmup - 1)):
         cb.fbs_solve(plan, Y, params)
-    torch.cuda.synchronize()
-
+    # per-kernel breakdown: one more solve, every launch bracketed by events
+    # (two event records per launch cost about 2% of a solve, so the timed
+    # steps below record the dominant kernel only)
     cb.kernel_timing(True)
+    cb.fbs_solve(plan, Y, params)
+    torch.cuda.synchronize()
+    cb.kernel_timing(False)
+    kall = cb.kernel_times()
+    dom = max(kall, key=lambda k: kall[k][1])
+    log("breakdown solve done; dominant kernel %s" % dom)
+
+    cb.kernel_timing(True, kernels=[dom])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -539,9 +548,7 @@ def main():
         "tv_sweep": (tv_launches[0] * iters[0], tv_launches[1] * iters[1]),
         "gather": (iters[0], iters[1]),
     }
-    dom = max(ktimes, key=lambda k: ktimes[k][1])
-    per_kernel = {k: {"launches": n // args.steps, "ms_per_step": tot / args.steps}
-                  for k, (n, tot) in ktimes.items()}
+    per_kernel = {k: {"launches": n, "ms_per_step": tot} for k, (n, tot) in kall.items()}
     roofline = None
     if dom in work:
         bound, per_step = work[dom]

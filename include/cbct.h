@@ -284,6 +284,12 @@ size_t cbct_fbs_footprint(const cbct_geom *g, const cbct_fbs_params *prm);
 #define CBCT_KERNEL_COUNT 8
 int cbct_kernel_timing(int32_t enable);
 int cbct_kernel_timing_read(int32_t kernel, int64_t *launches, double *total_ms);
+/* The same for the kernel kinds whose bit (1 << kind) is set in mask: a
+ * nonzero mask discards earlier records and records only those kinds (so
+ * that the others run without events); 0 stops recording.  CBCT_EINVAL for
+ * bits beyond CBCT_KERNEL_COUNT.  cbct_kernel_timing(e) is
+ * cbct_kernel_timing_select(e ? all kinds : 0). */
+int cbct_kernel_timing_select(uint32_t mask);
 
 /* Diagnostics: sustained fused multiply-add rate of this device, the
  * measured ceiling of the ALU-bound kernels.  Runs one kernel of

@@ -399,9 +399,17 @@ class FbsState:
         self.close()
 
 
-def kernel_timing(enable: bool):
-    """Start (clearing old records) or stop per-kernel HIP-event timing."""
-    check(_native.lib().cbct_kernel_timing(int(bool(enable))), "cbct_kernel_timing")
+def kernel_timing(enable: bool, kernels=None):
+    """Start (clearing old records) or stop per-kernel HIP-event timing.
+    kernels: names from _native.KERNELS to record (default all); the
+    others then run without events."""
+    if kernels is None or not enable:
+        check(_native.lib().cbct_kernel_timing(int(bool(enable))), "cbct_kernel_timing")
+        return
+    mask = 0
+    for k in kernels:
+        mask |= 1 << _native.KERNELS.index(k)
+    check(_native.lib().cbct_kernel_timing_select(mask), "cbct_kernel_timing_select")
 
 
 def kernel_times():

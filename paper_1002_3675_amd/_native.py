@@ -82,6 +82,7 @@ SIGNATURES = {
     "cbct_fbs_footprint": (ctypes.c_size_t, [ctypes.POINTER(cbct_geom),
                                              ctypes.POINTER(cbct_fbs_params)]),
     "cbct_kernel_timing": (ctypes.c_int, [_I32]),
+    "cbct_kernel_timing_select": (ctypes.c_int, [ctypes.c_uint32]),
     "cbct_kernel_timing_read": (ctypes.c_int, [_I32, ctypes.POINTER(ctypes.c_int64),
                                                ctypes.POINTER(_D)]),
     "cbct_probe_fma_rate": (ctypes.c_int, [_I32, ctypes.POINTER(_D), _P]),

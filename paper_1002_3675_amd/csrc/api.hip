@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <memory>
 #include <new>
 #include <string>
@@ -95,7 +96,7 @@ struct TimingRec {
     hipEvent_t a, b;
 };
 std::mutex g_tmu;
-bool g_timing = false;
+std::atomic<uint32_t> g_timing_mask{0};  // bit k: record kernel kind k
 std::vector<TimingRec> g_recs;
 std::vector<hipEvent_t> g_spare;
 
@@ -113,7 +114,7 @@ hipEvent_t take_event() {
 
 template <class F>
 hipError_t timed(int id, hipStream_t s, F &&launch) {
-    if (!g_timing) return launch();
+    if (!((g_timing_mask.load(std::memory_order_relaxed) >> id) & 1u)) return launch();
     hipEvent_t a, b;
     {
         std::lock_guard<std::mutex> lk(g_tmu);
@@ -130,17 +131,22 @@ hipError_t timed(int id, hipStream_t s, F &&launch) {
 
 }  // namespace cbct
 
-extern "C" int cbct_kernel_timing(int32_t enable) {
+extern "C" int cbct_kernel_timing_select(uint32_t mask) {
+    if (mask >> CBCT_KERNEL_COUNT) return set_error(CBCT_EINVAL, "unknown kernel kind in mask");
     std::lock_guard<std::mutex> lk(g_tmu);
-    if (enable) {
+    if (mask) {
         for (auto &r : g_recs) {
             g_spare.push_back(r.a);
             g_spare.push_back(r.b);
         }
         g_recs.clear();
     }
-    g_timing = enable != 0;
+    g_timing_mask.store(mask, std::memory_order_relaxed);
     return CBCT_OK;
+}
+
+extern "C" int cbct_kernel_timing(int32_t enable) {
+    return cbct_kernel_timing_select(enable ? (1u << CBCT_KERNEL_COUNT) - 1u : 0u);
 }
 
 extern "C" int cbct_kernel_timing_read(int32_t kernel, int64_t *launches, double *total_ms) {

@@ -101,6 +101,23 @@ def test_error_strings_without_gpu():
     assert lib.cbct_fbs_footprint(ctypes.byref(g), None) == 0
 
 
+def test_kernel_timing_selection_is_host_state():
+    """Selecting kernel kinds for event timing touches no device: unknown
+    kinds are refused, known masks and stopping are accepted, and reading
+    with no records gives zero launches."""
+    _native = _built()
+    lib = _native.lib()
+    assert lib.cbct_kernel_timing_select(1 << len(_native.KERNELS)) == _native.CBCT_EINVAL
+    assert lib.cbct_kernel_timing_select(1 << _native.KERNELS.index("cells")) == 0
+    assert lib.cbct_kernel_timing_select(0) == 0
+    assert lib.cbct_kernel_timing(1) == 0
+    assert lib.cbct_kernel_timing(0) == 0
+    n, t = ctypes.c_int64(-1), ctypes.c_double(-1.0)
+    assert lib.cbct_kernel_timing_read(_native.KERNELS.index("cells"), ctypes.byref(n),
+                                       ctypes.byref(t)) == 0
+    assert n.value == 0 and t.value == 0.0
+
+
 def test_representation_limits_are_rejected_before_the_device():
     """The transpose keeps cell indices and segment numbers in 16 bits:
     grids above 32000 voxels per axis, or a step so small that sample
