@@ -173,6 +173,38 @@ __device__ __forceinline__ double march_double(const double Q[3], const double D
 // keeps the bundle, and so the box, narrow in both detector directions;
 // 32-sample chunks then still fit 16 KB and spread the per-chunk box and
 // segment-origin work over twice the samples.
+// Sum of the trilinear samples m = ma .. mb of one chunk from the staged
+// box (row pitch RX, plane pitch RXY floats, base the LDS offset of the
+// segment origin's cell): seg_axis's coordinates and weights, the LDS offset
+// of the floors formed in float (exact: |offset| < 2^24), m counted in float
+// (exact below 2^24).  RXC > 0 fixes the row pitch at compile time.
+template <int RXC>
+__device__ __forceinline__ float staged_samples(const float *vol, int base, int RXr, int RXY,
+                                                float m, float mb, const float Df[3],
+                                                const float of[3]) {
+    const int RX = RXC > 0 ? RXC : RXr;
+    const float RXf = (float)RX, RXYf = (float)RXY;
+    float seg = 0.0f;
+    for (; m <= mb; m += 1.0f) {
+        const float lx = __builtin_fmaf(m, Df[0], of[0]);
+        const float ly = __builtin_fmaf(m, Df[1], of[1]);
+        const float lz = __builtin_fmaf(m, Df[2], of[2]);
+        const float fx = __builtin_floorf(lx), fy = __builtin_floorf(ly),
+                    fz = __builtin_floorf(lz);
+        const float wx = lx - fx, wy = ly - fy, wz = lz - fz;
+        const float *p = vol + base + (int)__builtin_fmaf(fz, RXYf, __builtin_fmaf(fy, RXf, fx));
+        const float *q = p + RXY;
+        const float c00 = p[0] + wx * (p[1] - p[0]);
+        const float c10 = p[RX] + wx * (p[RX + 1] - p[RX]);
+        const float c01 = q[0] + wx * (q[1] - q[0]);
+        const float c11 = q[RX] + wx * (q[RX + 1] - q[RX]);
+        const float c0 = c00 + wy * (c10 - c00);
+        const float c1 = c01 + wy * (c11 - c01);
+        seg += c0 + wz * (c1 - c0);
+    }
+    return seg;
+}
+
 constexpr int TILE_U = 16, TILE_V = 16, TILE_CH = 32;
 constexpr int TILE_LDS = 4096;  // floats
 constexpr int BOX_TAB = 64;     // chunk boxes computed together
@@ -306,31 +338,24 @@ __global__ __launch_bounds__(256) void k_project_tile(
             const SegOrigin o = seg_origin(Q, D, s);
             float seg = 0.0f;
             if (staged) {
-                const int RX = RXP;  // row pitch in LDS
-                const int RXY = RX * RY;
-                const float RXf = (float)RX, RXYf = (float)RXY;
-                const int base = (o.I[2] + 1 - b0[2]) * RXY + (o.I[1] + 1 - b0[1]) * RX +
+                const int RXY = RXP * RY;
+                const int base = (o.I[2] + 1 - b0[2]) * RXY + (o.I[1] + 1 - b0[1]) * RXP +
                                  (o.I[0] + 1 - b0[0]);
-                // m counts the samples in float (exact below 2^24)
-                const float mb = (float)(nb - s);
-                for (float m = (float)(na - s); m <= mb; m += 1.0f) {
-                    // seg_axis's coordinates and weights; the LDS offset of the
-                    // floors is formed in float (exact: |offset| < 2^24)
-                    const float lx = __builtin_fmaf(m, Df[0], o.f[0]);
-                    const float ly = __builtin_fmaf(m, Df[1], o.f[1]);
-                    const float lz = __builtin_fmaf(m, Df[2], o.f[2]);
-                    const float fx = __builtin_floorf(lx), fy = __builtin_floorf(ly),
-                                fz = __builtin_floorf(lz);
-                    const float wx = lx - fx, wy = ly - fy, wz = lz - fz;
-                    const float *p =
-                        vol + base + (int)__builtin_fmaf(fz, RXYf, __builtin_fmaf(fy, RXf, fx));
-                    const float c00 = p[0] + wx * (p[1] - p[0]);
-                    const float c10 = p[RX] + wx * (p[RX + 1] - p[RX]);
-                    const float c01 = p[RXY] + wx * (p[RXY + 1] - p[RXY]);
-                    const float c11 = p[RXY + RX] + wx * (p[RXY + RX + 1] - p[RXY + RX]);
-                    const float c0 = c00 + wy * (c10 - c00);
-                    const float c1 = c01 + wy * (c11 - c01);
-                    seg += c0 + wz * (c1 - c0);
+                const float ma = (float)(na - s), mb = (float)(nb - s);
+                // common row pitches as constants: the row offsets then sit in
+                // the LDS instructions' immediates
+                switch (RXP) {
+#define CBCT_PITCH(n)                                                                   \
+    case n:                                                                             \
+        seg = staged_samples<n>(vol, base, RXP, RXY, ma, mb, Df, o.f);                   \
+        break;
+                    CBCT_PITCH(5) CBCT_PITCH(7) CBCT_PITCH(9) CBCT_PITCH(11) CBCT_PITCH(13)
+                    CBCT_PITCH(15) CBCT_PITCH(17) CBCT_PITCH(19) CBCT_PITCH(21) CBCT_PITCH(23)
+                    CBCT_PITCH(25) CBCT_PITCH(27) CBCT_PITCH(29) CBCT_PITCH(31) CBCT_PITCH(33)
+                    CBCT_PITCH(35) CBCT_PITCH(37) CBCT_PITCH(39) CBCT_PITCH(41)
+#undef CBCT_PITCH
+                    default:
+                        seg = staged_samples<0>(vol, base, RXP, RXY, ma, mb, Df, o.f);
                 }
             } else {
                 const int base = (o.I[2] + 1) * pxy + (o.I[1] + 1) * px + (o.I[0] + 1);
