@@ -309,6 +309,15 @@ int cbct_probe_fma_rate(int32_t fp64, double *tflops_host, void *stream);
  * EINVAL for a NULL array or negative n.  No GPU work. */
 int cbct_kernel_config(int32_t *out_host, int32_t n);
 
+/* Diagnostics: the margin, in cells, by which the projector widens the box
+ * its tile's four corner rays span over a chunk of samples, so that the
+ * box holds every sample of the tile's other rays (they bulge out of the
+ * corner rays' hull by at most t a^2 / 2 for a sample at distance t from the
+ * source and a tile of angular half-diagonal a).  Written to *out_host for
+ * geometry g; EINVAL for an invalid geometry or NULL pointer.  No GPU
+ * work. */
+int cbct_projector_tile_margin(const cbct_geom *g, int32_t *out_host);
+
 const char *cbct_strerror(int code);
 const char *cbct_last_error(void);
 

@@ -454,6 +454,16 @@ def kernel_config() -> dict:
     return {k: int(buf[i]) for i, k in enumerate(names)}
 
 
+def projector_tile_margin(geom) -> int:
+    """Cells by which the projector widens a tile's corner-ray box
+    (cbct_projector_tile_margin; host arithmetic)."""
+    c, _ang = _to_c(geom)
+    out = ctypes.c_int32()
+    check(_native.lib().cbct_projector_tile_margin(ctypes.byref(c), ctypes.byref(out)),
+          "cbct_projector_tile_margin")
+    return int(out.value)
+
+
 def probe_fma_rate(fp64: bool = False) -> float:
     """Sustained non-packed FMA rate of the current device in TFLOP/s
     (float32, or float64 with fp64=True): the measured ALU ceiling."""

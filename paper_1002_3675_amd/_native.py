@@ -89,6 +89,7 @@ SIGNATURES = {
     "cbct_backproject_eq2": (ctypes.c_int, [_P, _P, _P, _P]),
     "cbct_log_counts": (ctypes.c_int, [_P, _P, _D, _D, _P, ctypes.c_int64, _P]),
     "cbct_kernel_config": (ctypes.c_int, [ctypes.POINTER(_I32), _I32]),
+    "cbct_projector_tile_margin": (ctypes.c_int, [ctypes.POINTER(cbct_geom), ctypes.POINTER(_I32)]),
     "cbct_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "cbct_last_error": (ctypes.c_char_p, []),
 }

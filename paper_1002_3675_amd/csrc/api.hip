@@ -279,6 +279,14 @@ size_t padded_of(const cbct_geom &g) { return (size_t)(g.nx + 2) * (g.ny + 2) * 
 
 // ================================================================= plans ===
 
+extern "C" int cbct_projector_tile_margin(const cbct_geom *g, int32_t *out_host) {
+    if (!out_host) return set_error(CBCT_EINVAL, "out_host is NULL");
+    const int rc = validate_geom(g);
+    if (rc) return rc;
+    *out_host = projector_tile_margin(*g);
+    return CBCT_OK;
+}
+
 extern "C" int cbct_plan_create(const cbct_geom *gin, cbct_plan **out) {
     try {
         if (!out) return set_error(CBCT_EINVAL, "out is NULL");

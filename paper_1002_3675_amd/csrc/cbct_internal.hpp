@@ -128,6 +128,7 @@ hipError_t launch_count_samples(const cbct_plan &p, unsigned long long *count, h
 // width and height in pixels, samples per chunk and LDS box in floats; the
 // transpose's brick in cells (x, y, z) and LDS table in pixels.
 void projector_config(int32_t out[4]);
+int projector_tile_margin(const cbct_geom &g);
 void cell_pass_config(int32_t out[4]);
 
 size_t project_partials_count(const cbct_plan &p);

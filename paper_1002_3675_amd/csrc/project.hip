@@ -465,8 +465,7 @@ dim3 tile_grid(const cbct_plan &p) { return dim3((unsigned)tile_count(p.g)); }
 // inside the bordered grid: at most the source's distance to the grid
 // centre (sad plus the grid's offset from the isocentre) plus half the
 // grid's diagonal.
-int tile_margin(const cbct_plan &p) {
-    const cbct_geom &g = p.g;
+int tile_margin(const cbct_geom &g) {
     const double hd = sqrt(pow(0.5 * TILE_U * g.au, 2) + pow(0.5 * TILE_V * g.av, 2));
     const double a = hd / g.sdd;
     const double tmax = g.sad + sqrt(pow(g.x_off, 2) + pow(g.y_off, 2) + pow(g.z_off, 2)) +
@@ -478,6 +477,8 @@ int tile_margin(const cbct_plan &p) {
 }
 
 }  // namespace
+
+int projector_tile_margin(const cbct_geom &g) { return tile_margin(g); }
 
 void projector_config(int32_t out[4]) {
     out[0] = TILE_U;
@@ -510,7 +511,7 @@ hipError_t launch_project(const cbct_plan &p, const T *fpad, const T *Y, T *out,
     if constexpr (sizeof(T) == 4) {
         hipLaunchKernelGGL(k_project_tile, tile_grid(p), dim3(256), 0, s, p.d_views, p.det,
                            p.grid, p.g.nu, p.g.nv, fpad, (int)elems, Y, out, partials,
-                           (float)p.g.step, tile_margin(p));
+                           (float)p.g.step, tile_margin(p.g));
     } else {
         if (partials) return hipErrorInvalidValue;  // no partial sums in double
         hipLaunchKernelGGL(k_project<T>, project_grid(p), dim3(PROJ_BX, PROJ_BY), 0, s,
