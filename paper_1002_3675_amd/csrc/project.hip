@@ -160,19 +160,6 @@ __device__ __forceinline__ double march_double(const double Q[3], const double D
     return acc;
 }
 
-// ---------------------------------------------------------------------------
-// Float projector with LDS-staged volume.  A workgroup owns a 16 x 16 tile of
-// detector pixels of one view; its 256 rays advance together through
-// chunks of TILE_CH consecutive sample indices.  For each chunk the four
-// corner rays of the tile bound (with a margin for the curvature of the
-// ray bundle) the box of cells every sample of the chunk can touch; that box
-// of the zero-bordered volume is staged in LDS with row-coalesced loads and
-// the eight trilinear taps of every sample are read from LDS.  A chunk whose
-// box does not fit falls back to loads from global memory.  The samples,
-// their cells and weights are exactly those of march_float.  A square tile
-// keeps the bundle, and so the box, narrow in both detector directions;
-// 32-sample chunks then still fit 16 KB and spread the per-chunk box and
-// segment-origin work over twice the samples.
 // Sum of the trilinear samples m = ma .. mb of one chunk from the staged
 // box (row pitch RX, plane pitch RXY floats, base the LDS offset of the
 // segment origin's cell): seg_axis's coordinates and weights, the LDS offset
@@ -205,6 +192,22 @@ __device__ __forceinline__ float staged_samples(const float *vol, int base, int 
     return seg;
 }
 
+// ---------------------------------------------------------------------------
+// Float projector with LDS-staged volume.  A workgroup owns a 16 x 16 tile of
+// detector pixels of one view; its 256 rays advance together through
+// chunks of TILE_CH consecutive sample indices.  For each chunk the four
+// corner rays of the tile bound (with a margin for the curvature of the
+// ray bundle) the box of cells every sample of the chunk can touch; that box
+// of the zero-bordered volume is loaded straight into LDS (buffer loads to
+// LDS, one z plane at a time) and the eight trilinear taps of every sample
+// are read from LDS.  The boxes of up to BOX_TAB chunks are computed
+// together, one chunk per lane, and kept in LDS.  A chunk whose box does
+// not fit falls back to loads from global memory.  The samples, their
+// cells and weights are exactly those of sample_cell and seg_axis (the
+// definitions the transpose shares).  A square tile
+// keeps the bundle, and so the box, narrow in both detector directions;
+// 32-sample chunks then still fit 16 KB and spread the per-chunk box and
+// segment-origin work over twice the samples.
 constexpr int TILE_U = 16, TILE_V = 16, TILE_CH = 32;
 constexpr int TILE_LDS = 4096;  // floats
 constexpr int BOX_TAB = 64;     // chunk boxes computed together

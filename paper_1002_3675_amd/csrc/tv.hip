@@ -9,7 +9,9 @@
 // (with a one-voxel halo) is staged once in LDS, p is computed once per
 // position of the tile and its low halo, and p_z of the plane below stays
 // in a register, so every voxel costs one read of z and g, one write, and
-// one reciprocal square root.
+// one reciprocal square root.  Arrays whose rows are a multiple of 4 voxels
+// and 16-byte aligned take k_tv_sweep4 (one wavefront per tile, four voxels
+// per lane, 16-byte loads and stores); others take the 256-lane k_tv_sweep.
 #include "cbct_internal.hpp"
 
 namespace cbct {
