@@ -342,7 +342,7 @@ def lowdose_sweep(torch, cb):
             Y = torch.as_tensor(case.Y, dtype=torch.float32, device="cuda")
             runs = [(mu, "matched") for mu in (5e-4, 1e-3, 2e-3)] + [(1e-3, "eq2")]
             for mu, grad in runs:
-                p = cb.FbsParams(mu=mu, iters=(30, 30), eps=1e-3, trace_energy=True,
+                p = cb.FbsParams(mu=mu, iters=(30, 30), eps=1e-3, trace_energy="final",
                                  gradient=grad)
                 cb.fbs_solve(plan, Y, p)  # beta setup for this data size
                 torch.cuda.synchronize()
@@ -374,7 +374,7 @@ def multigrid_schedules(torch, cb, plan, case, Y):
     rows = []
     for iters, tol in (((40,), 0.0), ((20, 20), 0.0), ((20, 20, 20), 0.0),
                        ((20, 20, 20, 20), 0.0), ((60, 60, 60), 3e-3), ((60, 60, 60), 1e-3)):
-        p = cb.FbsParams(mu=case.mu, iters=iters, eps=case.eps, trace_energy=True, tol=tol)
+        p = cb.FbsParams(mu=case.mu, iters=iters, eps=case.eps, trace_energy="final", tol=tol)
         cb.fbs_solve(plan, Y, p)  # beta of any new level, cached in its plan
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -402,7 +402,7 @@ def convergence_study(torch, cb, plan, case, Y):
 
     def run(name, pl, Yd, c, iters, tol):
         g = c.geom
-        p = cb.FbsParams(mu=c.mu, iters=iters, eps=c.eps, trace_energy=True, tol=tol)
+        p = cb.FbsParams(mu=c.mu, iters=iters, eps=c.eps, trace_energy="final", tol=tol)
         cb.fbs_solve(pl, Yd, cb.FbsParams(mu=c.mu, iters=iters, eps=c.eps))  # beta setup
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -493,10 +493,12 @@ def main():
     plan_c = cb.Plan(coarse_of(g))
     s_f, s_c = plan.samples, plan_c.samples
     iters = case.iters
-    params = cb.FbsParams(mu=case.mu, iters=iters, eps=case.eps, trace_energy=True)
-    # ray samples per solve: per level, iters+1 projections (one per
-    # iteration plus the final energy) and iters transposes
-    samples_per_step = (2 * iters[0] + 1) * s_c + (2 * iters[1] + 1) * s_f
+    # the timed solve computes the returned volume's energy only (per-iteration
+    # energies cost one host sync each, about 2% of a solve)
+    params = cb.FbsParams(mu=case.mu, iters=iters, eps=case.eps, trace_energy="final")
+    # ray samples per solve: per level, one projection and one transpose per
+    # iteration, plus the final energy's projection at the fine level
+    samples_per_step = 2 * iters[0] * s_c + (2 * iters[1] + 1) * s_f
 
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -536,14 +538,14 @@ def main():
     tv_launches = list(rep.n_inner_used)  # one launch per inner step
     sweeps = tv_launches[0] * iters[0] * nvox_c + tv_launches[1] * iters[1] * nvox_f
     work = {
-        "project": ("alu", FLOPS_PER_SAMPLE * ((iters[0] + 1) * s_c + (iters[1] + 1) * s_f)),
+        "project": ("alu", FLOPS_PER_SAMPLE * (iters[0] * s_c + (iters[1] + 1) * s_f)),
         "cells": ("alu", FLOPS_PER_SAMPLE * (iters[0] * s_c + iters[1] * s_f)),
         "tv_sweep": ("hbm", TV_BYTES_PER_VOXEL * sweeps),
         "gather": ("hbm", 4.0 * (8 + 1 + 1) * (iters[0] * nvox_c + iters[1] * nvox_f)),
     }
     # launches per level (coarse, fine) of each kernel in one solve
     mix = {
-        "project": (iters[0] + 1, iters[1] + 1),
+        "project": (iters[0], iters[1] + 1),
         "cells": (iters[0], iters[1]),
         "tv_sweep": (tv_launches[0] * iters[0], tv_launches[1] * iters[1]),
         "gather": (iters[0], iters[1]),

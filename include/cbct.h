@@ -200,7 +200,10 @@ int cbct_plan_lambda(const cbct_plan *p, int32_t n_iter, double *lambda_host,
  * power-iteration steps on that level.  n_inner[level] <= 0 selects
  * min(200, ceil(3 (1 + 4 sum_a h_a^-2 / (eps beta)))).  eps is the TV
  * smoothing (1/mm^2).  trace_energy = 1 computes E at the start of every
- * outer iteration and at the end (one host sync each).  gradient selects
+ * outer iteration and at the end of each level (one host sync each);
+ * trace_energy = 2 computes only the returned volume's E, at the end (one
+ * projection and one host sync); 0 computes none; other values are
+ * EINVAL.  gradient selects
  * Step 1's gradient of E2: 0 the exact transpose of the projector
  * (cbct_backproject; then E_eps never increases), 1 the paper's Eq. (2)
  * as printed (cbct_backproject_eq2, far cheaper, not matched). */
@@ -218,7 +221,7 @@ typedef struct cbct_fbs_params {
 } cbct_fbs_params;
 
 /* Filled by the solver.  E, E_eps, E1, E2 describe the returned volume
- * (computed only when trace_energy = 1, else zero).  level_iters[level]
+ * (computed only when trace_energy is 1 or 2, else zero).  level_iters[level]
  * counts the outer iterations made on each level, iters_done their sum;
  * change[level] is the relative change of the level's last iteration
  * (tol > 0 only, else 0).  trace, if not NULL, is a caller HOST array of

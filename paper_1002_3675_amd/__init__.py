@@ -21,7 +21,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
-from typing import Optional, Sequence, Tuple
+from typing import Optional, Sequence, Tuple, Union
 
 from . import _native
 from ._native import CbctError, cbct_fbs_params, cbct_fbs_report, cbct_geom, check
@@ -281,9 +281,17 @@ class FbsParams:
     beta: Optional[Sequence[float]] = None  # None / <= 0 -> power-iteration rule
     eps: float = 1e-3
     n_inner: Optional[Sequence[int]] = None  # None / <= 0 -> default rule
-    trace_energy: bool = False
+    trace_energy: Union[bool, str] = False  # True: E per iteration; "final": E at the end only
     gradient: str = "matched"             # "matched" (P^T) or "eq2" (the paper's Eq. (2))
     tol: float = 0.0                      # > 0: stop a level at this relative change
+
+    def trace_mode(self) -> int:
+        """cbct_fbs_params.trace_energy: 0 none, 1 per iteration, 2 final E."""
+        if isinstance(self.trace_energy, str):
+            if self.trace_energy != "final":
+                raise ValueError("trace_energy must be a bool or 'final'")
+            return 2
+        return int(bool(self.trace_energy))
 
     def to_c(self):
         n = len(self.iters)
@@ -297,7 +305,7 @@ class FbsParams:
             p.beta[l] = float(self.beta[l]) if self.beta is not None else 0.0
             p.n_inner[l] = int(self.n_inner[l]) if self.n_inner is not None else 0
         p.eps = float(self.eps)
-        p.trace_energy = int(bool(self.trace_energy))
+        p.trace_energy = self.trace_mode()
         if self.gradient not in ("matched", "eq2"):
             raise ValueError("gradient must be 'matched' or 'eq2'")
         p.gradient = 1 if self.gradient == "eq2" else 0
@@ -342,7 +350,7 @@ def fbs_solve(plan: Plan, Y, params: FbsParams, f0=None):
     rep = cbct_fbs_report()
     n_rows = sum(int(i) + 1 for i in params.iters)
     buf = None
-    if params.trace_energy:
+    if params.trace_mode() == 1:
         buf = (ctypes.c_double * (4 * n_rows))()
         rep.trace = ctypes.cast(buf, ctypes.POINTER(ctypes.c_double))
     with torch.cuda.device(Y.device):

@@ -839,6 +839,8 @@ int validate_params(const cbct_geom &g, const cbct_fbs_params *prm) {
     }
     if (prm->gradient != 0 && prm->gradient != 1)
         return set_error(CBCT_EINVAL, "gradient must be 0 (transpose) or 1 (Eq. (2))");
+    if (prm->trace_energy < 0 || prm->trace_energy > 2)
+        return set_error(CBCT_EINVAL, "trace_energy must be 0, 1 or 2");
     return CBCT_OK;
 }
 
@@ -1081,7 +1083,7 @@ extern "C" int cbct_fbs_step(cbct_fbs_state *st, int32_t n_iters, void *stream) 
             Level &L = st->lv[st->level];
             if (st->iter < L.iters && !L.stopped) {
                 if (left == 0) break;
-                const bool tr = st->prm.trace_energy != 0;
+                const bool tr = st->prm.trace_energy == 1;
                 if (tr) {
                     double row[4];
                     rc = level_residual(st, L, s, true, row);
@@ -1103,13 +1105,15 @@ extern "C" int cbct_fbs_step(cbct_fbs_state *st, int32_t n_iters, void *stream) 
                 }
                 continue;
             }
-            // level finished
-            if (st->prm.trace_energy) {
+            // level finished: its energy when traced, the returned volume's
+            // energy also when only that is asked for
+            const bool last = st->level == st->n_levels - 1;
+            if (st->prm.trace_energy == 1 || (st->prm.trace_energy == 2 && last)) {
                 double row[4];
                 rc = level_residual(st, L, s, true, row);
                 if (rc) break;
-                st->trace.insert(st->trace.end(), row, row + 4);
-                if (st->level == st->n_levels - 1) {
+                if (st->prm.trace_energy == 1) st->trace.insert(st->trace.end(), row, row + 4);
+                if (last) {
                     memcpy(st->final_e, row, sizeof(row));
                     st->have_final = true;
                 }

@@ -171,6 +171,14 @@ def test_solver_parameters_are_checked_on_the_host():
         cb.footprint(g, cb.FbsParams(iters=(5, 5)))
     with pytest.raises(ValueError):
         cb.FbsParams(iters=(1, 1, 1, 1, 1)).to_c()
+    assert cb.footprint(g, cb.FbsParams(iters=(5, 5), trace_energy="final")) > 0
+    bad = cb.FbsParams(iters=(5, 5)).to_c()
+    bad.trace_energy = 3
+    from paper_1002_3675_amd import _native
+    c, _ang = cb._to_c(g)
+    assert _native.lib().cbct_fbs_footprint(ctypes.byref(c), ctypes.byref(bad)) == 0
+    with pytest.raises(ValueError):
+        cb.FbsParams(trace_energy="every").to_c()
     assert cb.footprint(g, cb.FbsParams(iters=(5, 5), tol=-1.0)) == 0
     assert cb.footprint(g, cb.FbsParams(iters=(5, 5), tol=float("nan"))) == 0
     small = Geometry(6, 6, 3, 4.0, 4.0, 4.0, 16, 12, 3.2, 3.2, 1000.0, 1500.0, 4)

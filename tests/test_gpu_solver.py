@@ -165,6 +165,27 @@ def test_fbs_energy_monotone_on_gpu():
     assert float(f.min()) >= 0.0
 
 
+def test_final_energy_mode_matches_traced_solve():
+    """trace_energy="final" computes only the returned volume's energy: the
+    volume and that energy equal, bit for bit, those of the solve traced at
+    every iteration, and a solve without energies returns the same volume."""
+    torch = require_gpu()
+    import paper_1002_3675_amd as cb
+    case = tiny_case()
+    plan = cb.Plan(case.geom)
+    Y = to_dev(case.Y)
+    runs = {}
+    for mode in (True, "final", False):
+        runs[mode] = cb.fbs_solve(plan, Y, cb.FbsParams(mu=case.mu, iters=(3, 4), beta=(40.0, 40.0),
+                                                        trace_energy=mode))
+    (ft, rt), (ff, rf), (fn, rn) = runs[True], runs["final"], runs[False]
+    assert torch.equal(ft, ff) and torch.equal(ft, fn)
+    assert (rf.E, rf.E_eps, rf.E1, rf.E2) == (rt.E, rt.E_eps, rt.E1, rt.E2)
+    assert rf.E > 0 and rn.E == 0.0
+    assert rf.trace is None and len(rt.trace) == (3 + 1) + (4 + 1)
+    assert rt.trace[-1][0] == rt.E
+
+
 def test_step_api_equals_solve_bitwise():
     torch = require_gpu()
     import paper_1002_3675_amd as cb
