@@ -164,7 +164,8 @@ __device__ __forceinline__ double march_double(const double Q[3], const double D
 // box (row pitch RX, plane pitch RXY floats, base the LDS offset of the
 // segment origin's cell): seg_axis's coordinates and weights, the LDS offset
 // of the floors formed in float (exact: |offset| < 2^24), m counted in float
-// (exact below 2^24).  RXC > 0 fixes the row pitch at compile time.
+// (exact below 2^24); two samples per loop step, summed in order.  RXC > 0
+// fixes the row pitch at compile time.
 template <int RXC>
 __device__ __forceinline__ float staged_samples(const float *vol, int base, int RXr, int RXY,
                                                 float m, float mb, const float Df[3],
@@ -172,7 +173,7 @@ __device__ __forceinline__ float staged_samples(const float *vol, int base, int 
     const int RX = RXC > 0 ? RXC : RXr;
     const float RXf = (float)RX, RXYf = (float)RXY;
     float seg = 0.0f;
-    for (; m <= mb; m += 1.0f) {
+    auto sample = [&](float m) {
         const float lx = __builtin_fmaf(m, Df[0], of[0]);
         const float ly = __builtin_fmaf(m, Df[1], of[1]);
         const float lz = __builtin_fmaf(m, Df[2], of[2]);
@@ -188,7 +189,12 @@ __device__ __forceinline__ float staged_samples(const float *vol, int base, int 
         const float c0 = c00 + wy * (c10 - c00);
         const float c1 = c01 + wy * (c11 - c01);
         seg += c0 + wz * (c1 - c0);
+    };
+    for (; m + 1.0f <= mb; m += 2.0f) {
+        sample(m);
+        sample(m + 1.0f);
     }
+    if (m <= mb) sample(m);
     return seg;
 }
 
