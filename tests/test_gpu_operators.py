@@ -308,6 +308,38 @@ def test_fma_rate_probe_is_plausible():
     assert 1.0 < f64 <= 78.6 * 1.05, f64
 
 
+def test_kernel_timing_records_only_the_selected_kinds():
+    """Event timing restricted to the cell pass records its launches only;
+    timing every kind records the projector too; the results do not depend
+    on timing."""
+    torch = require_gpu()
+    import paper_1002_3675_amd as cb
+    g = tiny_geometry()
+    plan = _plan(g)
+    rng = np.random.default_rng(24)
+    f = to_dev(rng.uniform(0.0, 0.02, g.vol_shape))
+    y = to_dev(rng.uniform(0.0, 4.0, g.proj_shape))
+    ref_p, ref_t = plan.project(f), plan.backproject(y)
+    try:
+        cb.kernel_timing(True, kernels=["cells"])
+        p1, t1 = plan.project(f), plan.backproject(y)
+        torch.cuda.synchronize()
+        cb.kernel_timing(False)
+        kt = cb.kernel_times()
+        assert kt["cells"][0] == 1 and kt["cells"][1] > 0.0
+        assert kt["project"][0] == 0 and kt["gather"][0] == 0
+        cb.kernel_timing(True)
+        plan.project(f)
+        plan.backproject(y)
+        torch.cuda.synchronize()
+        cb.kernel_timing(False)
+        kt = cb.kernel_times()
+        assert kt["project"][0] == 1 and kt["cells"][0] == 1 and kt["gather"][0] == 1
+    finally:
+        cb.kernel_timing(False)
+    assert torch.equal(p1, ref_p) and torch.equal(t1, ref_t)
+
+
 def test_transpose_tables_are_prepared_once_and_shared_by_streams():
     """The plan prepares the transpose's geometry tables on its first call
     (here on a side stream) and every later call, on any stream, waits for
