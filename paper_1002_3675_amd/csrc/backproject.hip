@@ -17,7 +17,7 @@
 //     in the brick and the residual in LDS; each lane then visits the
 //     pixels whose rays can cross its cell, enumerates the samples of each
 //     such ray that fall in the cell, and accumulates r * (trilinear
-//     corner weight), in x-moment form, into eight register accumulators;
+//     corner weight), in xy-moment form, into eight register accumulators;
 //   * pass 2 (one lane per voxel): sum the matching corner of the eight
 //     cells that share the voxel, optionally fused with Step 1 of
 //     Algorithm A1, g = f - tau * P^T r.
@@ -208,34 +208,35 @@ __device__ __forceinline__ void add_corners(T acc[8], T rv, T wx, T wy, T wz) {
     t = a11 * wx; acc[6] += a11 - t; acc[7] += t;
 }
 
-// Float accumulation of r * corner weights in x-moment form: for each
-// (y, z) corner pair q = oy + 2 oz the cell keeps S_q = sum p_q and
-// T_q = sum p_q wx, p_q = r * (y weight) * (z weight); the corners are
-// (ox = 0) S_q - T_q and (ox = 1) T_q (moments_to_corners).  14 operations
-// per sample instead of 22.  The difference S_q - T_q carries an absolute
-// error of a few ulp of S_q, the cell's whole (y, z) mass, which is at most
-// the sum over the corners the voxel gather adds it to.
+// Float accumulation of r * corner weights in xy-moment form: for each z
+// corner oz the cell keeps S = sum b, X = sum b wx, Y = sum b wy and
+// XY = sum b wx wy, b = r * (z weight); the corners are (S - X) - (Y - XY),
+// X - XY, Y - XY and XY (moments_to_corners).  12 operations per sample
+// instead of 22.  The differences carry an absolute error of a few ulp of
+// S, the cell's mass on that z face, which is at most the sum over the
+// corners the voxel gather adds it to.
 __device__ __forceinline__ void add_moments(float acc[8], float rv, float wx, float wy,
                                             float wz) {
     const float b1 = rv * wz, b0 = rv - b1;
-    const float a01 = b0 * wy, a00 = b0 - a01;
-    const float a11 = b1 * wy, a10 = b1 - a11;
-    acc[0] += a00;
-    acc[1] = __builtin_fmaf(a00, wx, acc[1]);
-    acc[2] += a01;
-    acc[3] = __builtin_fmaf(a01, wx, acc[3]);
-    acc[4] += a10;
-    acc[5] = __builtin_fmaf(a10, wx, acc[5]);
-    acc[6] += a11;
-    acc[7] = __builtin_fmaf(a11, wx, acc[7]);
+    acc[0] += b0;
+    acc[1] = __builtin_fmaf(b0, wx, acc[1]);
+    acc[2] = __builtin_fmaf(b0, wy, acc[2]);
+    acc[3] = __builtin_fmaf(b0 * wx, wy, acc[3]);
+    acc[4] += b1;
+    acc[5] = __builtin_fmaf(b1, wx, acc[5]);
+    acc[6] = __builtin_fmaf(b1, wy, acc[6]);
+    acc[7] = __builtin_fmaf(b1 * wx, wy, acc[7]);
 }
 
-// Corner sums (index ox + 2 oy + 4 oz) from the x-moments of add_moments.
+// Corner sums (index ox + 2 oy + 4 oz) from the xy-moments of add_moments.
 __device__ __forceinline__ void moments_to_corners(const float m[8], float c[8]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        c[2 * q] = m[2 * q] - m[2 * q + 1];
-        c[2 * q + 1] = m[2 * q + 1];
+    for (int z = 0; z < 2; ++z) {
+        const float S = m[4 * z], X = m[4 * z + 1], Y = m[4 * z + 2], XY = m[4 * z + 3];
+        c[4 * z + 0] = (S - X) - (Y - XY);
+        c[4 * z + 1] = X - XY;
+        c[4 * z + 2] = Y - XY;
+        c[4 * z + 3] = XY;
     }
 }
 
