@@ -98,6 +98,23 @@ def test_wide_slices_match_oracle(name):
     assert rel_l2(b, want_b) <= TOL, rel_l2(b, want_b)
 
 
+def test_transpose_samples_a_hair_below_a_cell_face():
+    """An odd 3 x 3 detector has a central ray exactly parallel to -y (view
+    pi) or -x (view pi/2); with 0.1-voxel steps its in-segment coordinates
+    land a hair (below 2^-25) under a cell face, where the weight rounds up
+    to exactly 1.  The cell pass's fast membership test rejects those
+    samples and its second pass adds them back; without that pass this
+    transpose is 3e-3 away from the oracle's."""
+    require_gpu()
+    g = Geometry(16, 16, 3, 1.0, 1.0, 1.0, 3, 3, 1.0, 1.0, 200.0, 400.0, 8,
+                 angles=(math.pi, math.pi / 2) * 4, step=0.1)
+    rng = np.random.default_rng(3)
+    y = rng.uniform(0.5, 4.0, g.proj_shape).astype(np.float32).astype(np.float64)
+    f = to_np(_plan(g).backproject(to_dev(y)))
+    want = oracle.backproject(g, y)
+    assert rel_l2(f, want) <= TOL, rel_l2(f, want)
+
+
 def test_backproject_signed_residual():
     """Mixed-sign input (a residual) still meets the tolerance."""
     require_gpu()
