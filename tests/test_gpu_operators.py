@@ -98,6 +98,23 @@ def test_wide_slices_match_oracle(name):
     assert rel_l2(b, want_b) <= TOL, rel_l2(b, want_b)
 
 
+def test_projector_row_pitch_beyond_the_compiled_ones():
+    """The projector's staged loop is compiled for odd LDS row pitches 5 to
+    41.  Thin x voxels (0.25 mm) seen across a 16-pixel tile of 1 mm
+    footprint, with rays along y, need boxes about 60-75 cells wide in x
+    (still inside the LDS box: 4 mm of samples deep, two detector rows),
+    which take the generic loop."""
+    require_gpu()
+    g = Geometry(96, 24, 4, 0.25, 1.0, 1.0, 32, 2, 2.0, 2.0, 100.0, 200.0, 2,
+                 angles=(0.0, math.pi))
+    rng = np.random.default_rng(14)
+    f = rng.uniform(0.0, 0.02, g.vol_shape).astype(np.float32).astype(np.float64)
+    y = to_np(_plan(g).project(to_dev(f)))
+    want = oracle.project(g, f)
+    assert np.count_nonzero(want) > want.size // 2
+    assert rel_l2(y, want) <= TOL, rel_l2(y, want)
+
+
 def test_transpose_samples_a_hair_below_a_cell_face():
     """An odd 3 x 3 detector has a central ray exactly parallel to -y (view
     pi) or -x (view pi/2); with 0.1-voxel steps its in-segment coordinates
