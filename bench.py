@@ -123,6 +123,27 @@ def operator_rooflines(g, samples, ms_p, ms_pt):
     return out
 
 
+def diff_operators(torch, cb, dev, reps):
+    """P and P^T of the differentiation workload's geometry (128^3 at
+    1.5 mm, 60 views, 256x192 detector at 1.6 mm): ray samples per second and
+    the ALU fraction at 34 flop per sample."""
+    from workloads import diff_geometry
+    g = diff_geometry()
+    plan = cb.Plan(g)
+    s = plan.samples
+    f = torch.rand(g.vol_shape, device=dev) * 0.02
+    y = torch.rand(g.proj_shape, device=dev) * 4.0
+    yb, fb = torch.empty_like(y), torch.empty_like(f)
+    out = {"ray_samples": s}
+    for name, fn in (("P", lambda: plan.project(f, out=yb)),
+                     ("PT", lambda: plan.backproject(y, out=fb))):
+        ms = time_op(torch, fn, reps)
+        tfl = FLOPS_PER_SAMPLE * s / (ms * 1e-3) / 1e12
+        out[name] = {"ms": ms, "grays": s / (ms * 1e-3) / 1e9, "alu_frac": tfl / PEAK_ALU_TFLOPS}
+    del plan
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -579,6 +600,7 @@ def main():
     ms_pt = time_op(torch, lambda: plan.backproject(yr, out=fb), args.ops_reps)
     eq2 = eq2_comparison(torch, cb, plan, Y, params, f, rep, yr, fb, ms_pt, args.ops_reps)
     del fr, yr, yb, fb
+    ops_diff = diff_operators(torch, cb, dev, args.ops_reps)
     schedules = None if args.skip_schedules else multigrid_schedules(torch, cb, plan, case, Y)
 
     out = {
@@ -612,6 +634,7 @@ def main():
         "PT_fine_ms": ms_pt,
         "PT_fine_grays": s_f / (ms_pt * 1e-3) / 1e9,
         "operators_fine": operator_rooflines(g, s_f, ms_p, ms_pt),
+        "operators_128cubed_60views": ops_diff,
         "alu_measured_tflops": {"fp32_fma": cb.probe_fma_rate(False),
                                 "fp64_fma": cb.probe_fma_rate(True)},
         "paper_eq2": eq2,

@@ -304,11 +304,11 @@ int cbct_probe_fma_rate(int32_t fp64, double *tflops_host, void *stream);
 
 /* Diagnostics: the tunable sizes of the float kernels, written to the host
  * array out_host (at most n entries): [0] projector tile width and [1]
- * height in pixels, [2] samples per chunk, [3] LDS box capacity in floats;
- * [4..6] transpose brick in cells (x, y, z), [7] LDS table capacity in
- * pixels.  A tile chunk whose box exceeds [3], or a brick whose footprint
- * on the detector exceeds [7] pixels, reads global memory instead of LDS
- * (same results).  Returns the number of entries written (8 when n >= 8),
+ * height in pixels, [2] samples per box (the projector stages runs of
+ * such pieces), [3] LDS box capacity in floats; [4..6] transpose brick in
+ * cells (x, y, z), [7] LDS table capacity in pixels.  A piece whose box
+ * exceeds [3], or a brick whose footprint on the detector exceeds [7]
+ * pixels, reads global memory instead of LDS (same results).  Returns the number of entries written (8 when n >= 8),
  * EINVAL for a NULL array or negative n.  No GPU work. */
 int cbct_kernel_config(int32_t *out_host, int32_t n);
 

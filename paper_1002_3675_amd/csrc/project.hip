@@ -200,30 +200,91 @@ __device__ __forceinline__ float staged_samples(const float *vol, int base, int 
 
 // ---------------------------------------------------------------------------
 // Float projector with LDS-staged volume.  A workgroup owns a 16 x 16 tile of
-// detector pixels of one view; its 256 rays advance together through
-// chunks of TILE_CH consecutive sample indices.  For each chunk the four
-// corner rays of the tile bound (with a margin for the curvature of the
-// ray bundle) the box of cells every sample of the chunk can touch; that box
-// of the zero-bordered volume is loaded straight into LDS (buffer loads to
-// LDS, one z plane at a time) and the eight trilinear taps of every sample
-// are read from LDS.  The boxes of up to BOX_TAB chunks are computed
-// together, one chunk per lane, and kept in LDS.  A chunk whose box does
-// not fit falls back to loads from global memory.  The samples, their
+// detector pixels of one view; its 256 rays advance together through chunks
+// of consecutive sample indices.  The indices are cut into pieces of
+// TILE_SUB; for each piece the four corner rays of the tile bound (with a
+// margin for the curvature of the ray bundle) the box of cells every sample
+// of the piece can touch.  The boxes of up to BOX_TAB pieces are computed
+// together, one piece per lane, and then grouped into chunks, one aligned
+// block of TILE_MERGE pieces per lane: a chunk is a run of pieces of one
+// block whose boxes' bounding box fits TILE_LDS floats, or a run of pieces
+// whose own boxes do not fit.  A fitting chunk's box of the zero-bordered
+// volume is loaded straight into LDS (buffer loads to LDS, one z plane at a
+// time) and the eight trilinear taps of every sample are read from LDS; an
+// unfitting chunk reads its taps from global memory.  The samples, their
 // cells and weights are exactly those of sample_cell and seg_axis (the
-// definitions the transpose shares).  A square tile
-// keeps the bundle, and so the box, narrow in both detector directions;
-// 32-sample chunks then still fit 16 KB and spread the per-chunk box and
-// segment-origin work over twice the samples.
-constexpr int TILE_U = 16, TILE_V = 16, TILE_CH = 32;
-constexpr int TILE_LDS = 4096;  // floats
-constexpr int BOX_TAB = 64;     // chunk boxes computed together
+// definitions the transpose shares), whatever the chunking.  A square tile
+// keeps the bundle, and so the box, narrow in both detector directions.
+// Where a tile spans many cells (pixels near the voxel size) single pieces
+// still fit; where it spans few, runs spread the per-chunk staging and
+// segment-origin work over more samples.
+constexpr int TILE_U = 16, TILE_V = 16;
+constexpr int TILE_SUB = 16;    // samples per box
+constexpr int TILE_MERGE = 8;   // boxes per chunk at most
+constexpr int TILE_LDS = 5632;  // floats (larger boxes stage more slowly than they save)
+constexpr int BOX_TAB = 128;    // boxes computed together
+static_assert(SEG % (TILE_SUB * TILE_MERGE) == 0, "a block of pieces lies inside one segment");
+static_assert(BOX_TAB % TILE_MERGE == 0 && BOX_TAB <= 256, "whole blocks per box table");
+static_assert(TILE_LDS < (1 << 13), "the plane row division is exact below 2^13");
+
+__device__ __forceinline__ void unpack_box(int4 e, int b0[3], int b1[3]) {
+    const int pk[3] = {e.x, e.y, e.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        b0[a] = (int)(short)(pk[a] & 0xffff);
+        b1[a] = pk[a] >> 16;
+    }
+}
+
+// Whether the box fits the LDS box with its odd row pitch (products taken
+// in an order that cannot overflow: every extent is below 2^16).
+__device__ __forceinline__ bool box_fits(const int b0[3], const int b1[3]) {
+    const int RX = b1[0] - b0[0] + 1, RY = b1[1] - b0[1] + 1, RZ = b1[2] - b0[2] + 1;
+    if (RX <= 0 || RY <= 0 || RZ <= 0) return false;
+    const int npl = (RX | 1) * RY;
+    return npl <= TILE_LDS && npl * RZ <= TILE_LDS;
+}
+
+// Groups the pieces [q0, q1) of one block of the table into chunks: the
+// entry of a chunk's first piece takes the chunk's box and, in w, its
+// length in pieces (negative for a chunk read from global memory).
+__device__ __forceinline__ void group_block(int4 *tab, int q0, int q1) {
+    for (int q = q0; q < q1;) {
+        int b0[3], b1[3];
+        unpack_box(tab[q], b0, b1);
+        const bool fits = box_fits(b0, b1);
+        int e = q + 1;
+        for (; e < q1; ++e) {
+            int u0[3], u1[3];
+            unpack_box(tab[e], u0, u1);
+            if (fits) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    u0[a] = min(u0[a], b0[a]);
+                    u1[a] = max(u1[a], b1[a]);
+                }
+                if (!box_fits(u0, u1)) break;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    b0[a] = u0[a];
+                    b1[a] = u1[a];
+                }
+            } else if (box_fits(u0, u1)) {
+                break;
+            }
+        }
+        tab[q] = make_int4((b0[0] & 0xffff) | (b1[0] << 16), (b0[1] & 0xffff) | (b1[1] << 16),
+                           (b0[2] & 0xffff) | (b1[2] << 16), fits ? e - q : q - e);
+        q = e;
+    }
+}
 
 __global__ __launch_bounds__(256) void k_project_tile(
     const ViewConst *__restrict__ views, DetConst dc, GridConst gc, int nu, int nv,
     const float *__restrict__ fp, int fp_elems, const float *__restrict__ Y,
     float *__restrict__ out, double *__restrict__ partials, float step, int margin) {
     __shared__ float vol[TILE_LDS];
-    __shared__ int4 boxes[BOX_TAB];  // chunk boxes, packed (b0 | b1 << 16 per axis)
+    __shared__ int4 boxes[BOX_TAB];  // piece boxes, packed b0 | b1 << 16 per axis
     __shared__ int red[2][4];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
@@ -257,15 +318,16 @@ __global__ __launch_bounds__(256) void k_project_tile(
     const __amdgpu_buffer_rsrc_t gvol =
         __builtin_amdgcn_make_buffer_rsrc((void *)fp, (short)0, fp_elems * 4, 0x00020000);
     double acc = 0.0;
-    // chunk c holds the sample indices nc0 + TILE_CH c .. nc0 + TILE_CH c + TILE_CH - 1
-    const int nc0 = lo & ~(TILE_CH - 1);
-    const int nchunks = hi >= nc0 ? (hi - nc0) / TILE_CH + 1 : 0;
-    for (int cg = 0; cg < nchunks; cg += BOX_TAB) {
+    // piece c holds the sample indices nc0 + TILE_SUB c .. nc0 + TILE_SUB (c + 1) - 1;
+    // blocks of pieces start at multiples of TILE_SUB * TILE_MERGE
+    const int nc0 = lo & ~(TILE_SUB * TILE_MERGE - 1);
+    const int npieces = hi >= nc0 ? (hi - nc0) / TILE_SUB + 1 : 0;
+    for (int cg = 0; cg < npieces; cg += BOX_TAB) {
         __syncthreads();  // readers of the previous group's boxes are done
-        if (tid < BOX_TAB && cg + tid < nchunks) {
-            // box of padded cells [b0, b1] per axis touched by chunk cg + tid,
+        if (tid < BOX_TAB && cg + tid < npieces) {
+            // box of padded cells [b0, b1] per axis touched by piece cg + tid,
             // from the tile's four corner rays
-            const int nc = nc0 + TILE_CH * (cg + tid);
+            const int nc = nc0 + TILE_SUB * (cg + tid);
             const int ci0 = tu * TILE_U, ci1 = min(ci0 + TILE_U - 1, nu - 1);
             const int cj0 = tv * TILE_V, cj1 = min(cj0 + TILE_V - 1, nv - 1);
             double Dc[4][3], Qc[3];
@@ -280,7 +342,7 @@ __global__ __launch_bounds__(256) void k_project_tile(
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const double qa = Qc[a] + (double)nc * Dc[c][a];
-                    const double qb = Qc[a] + (double)(nc + TILE_CH - 1) * Dc[c][a];
+                    const double qb = Qc[a] + (double)(nc + TILE_SUB - 1) * Dc[c][a];
                     qmin = fmin(qmin, fmin(qa, qb));
                     qmax = fmax(qmax, fmax(qa, qb));
                 }
@@ -294,25 +356,27 @@ __global__ __launch_bounds__(256) void k_project_tile(
             boxes[tid] = make_int4(pk[0], pk[1], pk[2], 0);
         }
         __syncthreads();
-        const int cend = min(nchunks, cg + BOX_TAB);
-        for (int c = cg; c < cend; ++c) {
-            const int nc = nc0 + TILE_CH * c;
-            const int4 bp = boxes[c - cg];
+        const int cend = min(npieces, cg + BOX_TAB);
+        if (tid < BOX_TAB / TILE_MERGE && cg + TILE_MERGE * tid < cend)
+            group_block(boxes, TILE_MERGE * tid, min(TILE_MERGE * (tid + 1), cend - cg));
+        __syncthreads();
+        for (int c = cg; c < cend;) {
+            const int nc = nc0 + TILE_SUB * c;
+            const int4 ent = boxes[c - cg];
             // identical in every lane: kept in scalar registers
-            const int pk[3] = {__builtin_amdgcn_readfirstlane(bp.x),
-                               __builtin_amdgcn_readfirstlane(bp.y),
-                               __builtin_amdgcn_readfirstlane(bp.z)};
             int b0[3], b1[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                b0[a] = (int)(short)(pk[a] & 0xffff);
-                b1[a] = pk[a] >> 16;
-            }
+            unpack_box(make_int4(__builtin_amdgcn_readfirstlane(ent.x),
+                                 __builtin_amdgcn_readfirstlane(ent.y),
+                                 __builtin_amdgcn_readfirstlane(ent.z), 0),
+                       b0, b1);
+            const int run = __builtin_amdgcn_readfirstlane(ent.w);
+            const bool staged = run > 0;
+            const int len = TILE_SUB * (staged ? run : -run);
+            c += staged ? run : -run;
             const int RX = b1[0] - b0[0] + 1, RY = b1[1] - b0[1] + 1, RZ = b1[2] - b0[2] + 1;
             // LDS rows have an odd pitch, so rays spread across rows (views whose
             // rays run along x) do not pile onto one bank
             const int RXP = RX | 1;
-            const bool staged = RX > 0 && RY > 0 && RZ > 0 && RXP * RY * RZ <= TILE_LDS;
             __syncthreads();  // the previous chunk's readers are done
             if (staged) {
                 // Plane z of the box is RXP * RY consecutive LDS elements, x
@@ -341,7 +405,7 @@ __global__ __launch_bounds__(256) void k_project_tile(
                 __builtin_amdgcn_s_waitcnt(0);  // the loads have landed in LDS
             }
             __syncthreads();
-            const int na = max(n0, nc), nb = min(n1, nc + TILE_CH - 1);
+            const int na = max(n0, nc), nb = min(n1, nc + len - 1);
             if (na > nb) continue;
             const int s = nc & ~(SEG - 1);
             const SegOrigin o = seg_origin(Q, D, s);
@@ -492,7 +556,7 @@ int projector_tile_margin(const cbct_geom &g) { return tile_margin(g); }
 void projector_config(int32_t out[4]) {
     out[0] = TILE_U;
     out[1] = TILE_V;
-    out[2] = TILE_CH;
+    out[2] = TILE_SUB;
     out[3] = TILE_LDS;
 }
 

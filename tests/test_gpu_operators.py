@@ -66,7 +66,7 @@ def test_backproject_matches_oracle(name, g):
 WIDE = {
     "staged": Geometry(2900, 2900, 2, 1.0, 1.0, 1.0, 40, 6, 0.4, 0.4, 2500.0, 3000.0, 2,
                        angles=(0.3, 1.9)),
-    "global": Geometry(2900, 2900, 2, 0.1, 0.1, 0.1, 40, 6, 3.2, 0.1, 600.0, 1000.0, 2,
+    "global": Geometry(2900, 2900, 2, 0.1, 0.1, 0.1, 40, 6, 12.8, 0.1, 600.0, 1000.0, 2,
                        angles=(0.3, 1.9)),
 }
 
@@ -78,7 +78,7 @@ def test_wide_slices_match_oracle(name):
     _log("wide-slice parity %s" % name)
     assert (g.nx + 2) * (g.ny + 2) > 2 ** 23
     if name == "global":
-        # lower bound of a chunk box (as in fallback_margins): beyond the LDS box
+        # lower bound of a piece's box (as in fallback_margins): beyond the LDS box
         import paper_1002_3675_amd as cb
         cfg = cb.kernel_config()
         half = 0.5 * math.sqrt((g.nx * g.hx) ** 2 + (g.ny * g.hy) ** 2 + (g.nz * g.hz) ** 2)
@@ -274,9 +274,9 @@ def test_diff_size_transpose_matches_oracle():
 PT_FALLBACK = Geometry(16, 16, 16, 2.0, 2.0, 2.0, 256, 256, 0.2, 0.2, 300.0, 450.0, 3,
                        angles=(0.3, 1.9, 4.0))
 # P: 8 mm pixels over 1 mm voxels, so the rays of one tile fan over the
-# whole grid cross-section and no chunk's box fits the LDS box: every tap is
+# whole grid cross-section and no piece's box fits the LDS box: every tap is
 # read from the bordered volume in global memory.
-P_FALLBACK = Geometry(48, 48, 48, 1.0, 1.0, 1.0, 24, 16, 8.0, 8.0, 300.0, 450.0, 3,
+P_FALLBACK = Geometry(64, 64, 64, 1.0, 1.0, 1.0, 24, 16, 8.0, 8.0, 300.0, 450.0, 3,
                       angles=(0.2, 2.2, 4.5))
 
 
@@ -297,8 +297,9 @@ def fallback_margins(cfg):
     g = P_FALLBACK
     # a tile's rays span tile * pitch * d / sdd at distance d from the
     # source; inside the grid d >= sad - half, and the box is clipped to
-    # the bordered grid; a chunk advances chunk * step along the ray, at
-    # least chunk * step / sqrt(3) along its dominant axis
+    # the bordered grid; a piece (the samples of the smallest box) advances
+    # piece * step along the ray, at least piece * step / sqrt(3) along its
+    # dominant axis
     half = 0.5 * math.sqrt((g.nx * g.hx) ** 2 + (g.ny * g.hy) ** 2 + (g.nz * g.hz) ** 2)
     d = g.sad - half
     span_u = min(cfg["tile_u"] * g.au * d / g.sdd / g.hx, g.nx + 2)
