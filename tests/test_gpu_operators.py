@@ -252,6 +252,28 @@ def test_diff_size_projection_matches_oracle():
     assert rel_l2(y, oracle.project(g, f)) <= TOL
 
 
+def test_thick_slice_serving_size_matches_oracle():
+    """256x256x64 at 1 x 1 x 2.5 mm with a 256x192 detector at 1.552 mm (the
+    serving mix's middle class), on six views including the diagonals: the
+    projector's pieces group into runs of several lengths here, some of
+    them unfitting, and the transpose's footprints are narrower than at
+    the head size."""
+    require_gpu()
+    from workloads import serving_geometries
+    g0 = serving_geometries()["256x256x64"]
+    g = dataclasses.replace(g0, n_views=6,
+                            angles=(0.0, math.pi / 4, 1.1, 2.9, 3 * math.pi / 4 + 0.1, 5.0))
+    _log("thick-slice parity %dx%dx%d" % (g.nx, g.ny, g.nz))
+    plan = _plan(g)
+    rng = np.random.default_rng(23)
+    f = rng.uniform(0, 0.02, g.vol_shape).astype(np.float32).astype(np.float64)
+    y = to_np(plan.project(to_dev(f)))
+    assert rel_l2(y, oracle.project(g, f)) <= TOL
+    r = rng.uniform(-1, 4, g.proj_shape).astype(np.float32).astype(np.float64)
+    b = to_np(plan.backproject(to_dev(r)))
+    assert rel_l2(b, oracle.backproject(g, r)) <= TOL
+
+
 def test_diff_size_transpose_matches_oracle():
     """128^3, 60 views, 256x192 (the differentiation workload)."""
     require_gpu()
