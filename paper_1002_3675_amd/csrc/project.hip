@@ -236,8 +236,10 @@ __device__ __forceinline__ void unpack_box(int4 e, int b0[3], int b1[3]) {
     }
 }
 
-// Whether the box fits the LDS box with its odd row pitch (products taken
-// in an order that cannot overflow: every extent is below 2^16).
+// Whether the box fits the LDS box with its odd row pitch.  No product
+// overflows: grid dimensions are at most 32000, so every extent is below
+// 2^15 and a plane below 2^30, and the box is formed only for a plane that
+// fits.
 __device__ __forceinline__ bool box_fits(const int b0[3], const int b1[3]) {
     const int RX = b1[0] - b0[0] + 1, RY = b1[1] - b0[1] + 1, RZ = b1[2] - b0[2] + 1;
     if (RX <= 0 || RY <= 0 || RZ <= 0) return false;
