@@ -281,7 +281,9 @@ __device__ __forceinline__ void group_block(int4 *tab, int q0, int q1) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_project_tile(
+// At most 80 VGPRs: six wavefronts per SIMD (six groups of 24 KB of LDS per
+// CU) instead of the five that the unconstrained 95 allow.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_project_tile(
     const ViewConst *__restrict__ views, DetConst dc, GridConst gc, int nu, int nv,
     const float *__restrict__ fp, int fp_elems, const float *__restrict__ Y,
     float *__restrict__ out, double *__restrict__ partials, float step, int margin) {
